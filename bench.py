@@ -1,0 +1,153 @@
+"""Benchmark of the fused d2v72 collide-and-stream step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--precision fp32|fp64]
+                    [--no-cpu-baseline]
+
+A step is one time step of the whole grid (pull streaming, moments, Landau frame,
+inversion, fifth-order equilibrium, relaxation) on device-resident populations.
+Prints one JSON line: MLUPS (cell updates per second / 1e6), the roofline of the
+step kernel (algorithmic HBM bytes per launch / measured launch time against the
+8 TB/s HBM peak) and the CPU oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+WORKLOADS = {
+    # name: (configuration text, builder)
+    "fd_hotspot_2048": "Fermi-Dirac hot spot 2048x2048, Gaussian theta bump (amp 0.3, sigma 64) on theta = 1, "
+                       "seeded fugacity in [0.5, 2], tau = 2/theta + 0.2546, open boundaries",
+    "taylor_green_512": "Taylor-Green vortex 512x512 periodic, MJ, u0 = 0.05, theta = n = 1, tau = 0.8",
+    "be_hotspot_8192": "Bose-Einstein 8192x8192, 16 seeded Gaussian theta/fugacity bumps, tau = 2/theta + 0.2546, open",
+    "riemann_1024x4": "Riemann shock tube MJ 1024x4, n 1.0/0.139, theta = 1, tau = 0.9, x open, y periodic",
+}
+
+
+def build_workload(name, device):
+    import workloads
+    if name == "fd_hotspot_2048":
+        params, fields = workloads.hotspot_fd(L=2048, device=device)
+    elif name == "taylor_green_512":
+        params, fields = workloads.taylor_green(L=512, tau=0.8, device=device)
+        params["stats"] = "MJ"
+    elif name == "be_hotspot_8192":
+        params, fields = workloads.hotspot_be(L=8192, device=device)
+    elif name == "riemann_1024x4":
+        params, fields = workloads.riemann(device=device)
+        params["stats"] = "MJ"
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    return params, fields
+
+
+def cpu_baseline(name, budget_s=15.0):
+    """Time the FP64 oracle (as it stands) on a bounded sample: a 64 x 64 window of
+    the same workload's initial fields, as many steps as fit the budget."""
+    import numpy as np
+    try:
+        import threadpoolctl
+        threads = max([1] + [i.get("num_threads", 1) for i in threadpoolctl.threadpool_info()])
+    except Exception:
+        threads = 1
+    from oracle import lattice as L
+    params, fields = build_workload(name, "cpu")
+    nx, ny = params["nx"], params["ny"]
+    w = min(64, nx)
+    h = min(64, ny)
+    x0, y0 = (nx - w) // 2, (ny - h) // 2
+    sub = {k: v[y0:y0 + h, x0:x0 + w].numpy() for k, v in fields.items()}
+    bc = dict(zip(("xlo", "xhi", "ylo", "yhi"), ("open",) * 4))
+    op = L.Params(stats=params.get("stats", "MJ"), nx=w, ny=h, tau_mode=params.get("tau_mode", "const"),
+                  tau=params.get("tau", 1.0), tau_a=params.get("tau_a", 2.0), tau_b=params.get("tau_b", 0.2546), bc=bc)
+    f = L.init_state(op, sub["theta"], sub["ux"], sub["uy"], n=sub.get("n"), z=sub.get("z"))
+    steps = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        f, _ = L.step(f, op)
+        steps += 1
+    dt = time.perf_counter() - t0
+    return dict(value=w * h * steps / dt / 1e6, unit="MLUPS", cores=int(threads), kind="oracle",
+                sample=f"{w}x{h} window of the workload's initial fields, open boundaries, {steps} FP64 steps "
+                       f"in {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--workload", default="fd_hotspot_2048", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the domain-decomposed design is described in DESIGN.md)", file=sys.stderr)
+        raise SystemExit(2)
+
+    import torch
+    from paper_1709_09073_amd import rlbm
+
+    dev = "cuda"
+    params, fields = build_workload(args.workload, dev)
+    params["precision"] = args.precision
+    print(f"[bench] workload={args.workload} precision={args.precision} grid={params['nx']}x{params['ny']} "
+          f"warmup={args.warmup} steps={args.steps}", file=sys.stderr, flush=True)
+    sim = rlbm.Sim(params, fields)
+    del fields
+    sim.step(args.warmup)
+    sim.sync()
+    torch.cuda.synchronize()
+    stream = sim.stream
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    sim.step(args.steps)
+    e1.record(stream)
+    e1.synchronize()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    status = sim.status()
+    ncell = params["nx"] * params["ny"]
+    mlups = ncell * args.steps / (ms * 1e-3) / 1e6
+    elem = 8 if args.precision == "fp64" else 4
+    bytes_per_launch = 2 * 72 * elem * ncell
+    launch_s = ms * 1e-3 / args.steps
+    achieved = bytes_per_launch / launch_s / 1e9
+    sim.close()
+    print(f"[bench] {mlups:.1f} MLUPS, {achieved:.0f} GB/s, status=0x{status:x}", file=sys.stderr, flush=True)
+
+    out = {
+        "metric": "MLUPS at 5th-order quadrature + % HBM peak; BF16/MLP vs plain FP32 at fixed err",
+        "value": round(mlups, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "description": WORKLOADS[args.workload],
+                   "grid": [params["nx"], params["ny"]], "statistic": params.get("stats", "MJ"),
+                   "order": 5, "lattice": "d2v72", "populations": args.precision, "inversion_guess": "fixed",
+                   "status_bits": status},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "algorithmic_bytes_per_launch": bytes_per_launch, "kernel": "k_step"},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.workload)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,144 @@
+/*
+ * rlbm.h -- C ABI of the MI355X (gfx950) library for the fully dissipative
+ * two-dimensional ultra-relativistic lattice Boltzmann method on the d2v72
+ * lattice (Coelho, Mendoza, Doria, Herrmann, arXiv:1709.09073).
+ *
+ * Problem statement (Sec. 2 and Sec. 3 of the paper): given initial macroscopic
+ * fields per cell -- particle density n or fugacity z, temperature theta and
+ * velocity u -- a statistic (Maxwell-Juttner, Fermi-Dirac or Bose-Einstein), a
+ * relaxation time (constant, or tau = tau_a/theta + tau_b as in Sec. 3.2 and
+ * Sec. 3.5) and boundary rules, evolve the populations by the discrete
+ * Anderson-Witting equation (Sec. 2.1) with bilinear pull streaming (Sec. 2.4)
+ * and report n, eps (P = eps/2), theta, z, u and the heat flux q (Eqs.
+ * density-eq, theta-eq, n-eps-eq, heat-eq2).
+ *
+ * Conventions
+ *  - Populations: structure of arrays f[q][y][x], q = 6*n + k with direction
+ *    n = 0..11 (angle n*pi/6; the paper's label i = n + 1) and radial shell
+ *    k = 0..5; cell (x, y) at integer coordinates, x fastest.  The element type
+ *    is double (RLBM_FP64) or float (RLBM_FP32).  Each population buffer holds
+ *    72*nx*ny elements.
+ *  - The stored state is the post-collision population.  One step is: pull
+ *    streaming, moments N^mu and T^{mu nu}, Landau frame (Eq. eigen-eq), density
+ *    (Eq. density-eq), inversion to (theta, z), relaxation time, fifth-order
+ *    equilibrium (Eq. expansion-eq), relaxation; fixed-temperature wall cells
+ *    are then set to f^eq(n_nb, theta_wall, u_nb) with n and u taken from the
+ *    first fluid cell (Sec. 3.3).
+ *  - Field arrays are double, nx*ny elements, row-major [y][x].
+ *  - Ownership: the caller allocates every population and field buffer in
+ *    device memory and keeps it alive until rlbm_free.  The library allocates
+ *    only a small status word per context.  No pointer passed in is freed by
+ *    the library.
+ *  - Errors: every int-returning call returns RLBM_OK (0) or a negative code;
+ *    rlbm_strerror gives its text.  No C++ exception crosses this interface.
+ *    Domain failures found inside kernels (non-positive n or eps, |u| >= 1,
+ *    a Bose-Einstein state beyond the condensation bound, an inversion outside
+ *    its table range, a solve that did not converge) set bits of a device
+ *    status word, reported as RLBM_EDOMAIN by the next rlbm_sync or
+ *    rlbm_moments (which then clear it); rlbm_status returns the bits.
+ *  - Streams: all work is enqueued on the stream given in rlbm_params
+ *    (a hipStream_t, NULL for the default stream) and is asynchronous except
+ *    rlbm_sync, rlbm_status and rlbm_moments (which synchronises).
+ */
+#ifndef RLBM_H
+#define RLBM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum rlbm_status_code {
+    RLBM_OK = 0,
+    RLBM_EINVAL = -1,     /* bad argument: shape, order, statistic, precision, tau, boundary */
+    RLBM_EDOMAIN = -2,    /* a kernel flagged a state outside the method's domain */
+    RLBM_EHIP = -3,       /* a HIP runtime call failed */
+    RLBM_ENONFINITE = -4, /* a kernel produced a non-finite field */
+    RLBM_ENOTIMPL = -5    /* valid request this build does not support */
+};
+
+enum rlbm_stats { RLBM_MJ = 0, RLBM_FD = 1, RLBM_BE = 2 };         /* Eqs. mj-w-eq, fd-w-eq, be-w-eq */
+enum rlbm_precision { RLBM_FP64 = 0, RLBM_FP32 = 1 };
+enum rlbm_tau_mode { RLBM_TAU_CONST = 0, RLBM_TAU_INV_THETA = 1 };  /* tau, or tau_a/theta + tau_b */
+enum rlbm_bc {
+    RLBM_BC_PERIODIC = 0, /* wrap (both sides of an axis must be periodic) */
+    RLBM_BC_OPEN = 1,     /* zero gradient: a pull from outside takes the nearest edge cell */
+    RLBM_BC_WALL_T = 2    /* fixed-temperature wall cell on the edge column (x sides only) */
+};
+enum rlbm_guess { RLBM_GUESS_FIXED = 0, RLBM_GUESS_MLP = 1 };       /* FD/BE inversion start */
+
+/* status-word bits (rlbm_status) */
+#define RLBM_FLAG_NONPOSITIVE  0x1u  /* n <= 0, eps <= 0 or a non-finite moment */
+#define RLBM_FLAG_SUPERLUMINAL 0x2u  /* |u| >= 1 */
+#define RLBM_FLAG_CONDENSED    0x4u  /* BE: 2n^3/(pi eps^2) >= h(z_c); z clamped to z_c */
+#define RLBM_FLAG_RANGE        0x8u  /* FD: ln z above the table range (12.125) */
+#define RLBM_FLAG_NOCONV       0x10u /* Landau or inversion iteration hit its limit */
+
+typedef struct rlbm_params {
+    int32_t nx, ny;          /* grid size, both >= 2 (walls need nx >= 4) */
+    int32_t stats;           /* rlbm_stats */
+    int32_t order;           /* expansion order; this build supports 5 */
+    int32_t precision;       /* rlbm_precision: element type of f_a, f_b */
+    int32_t tau_mode;        /* rlbm_tau_mode */
+    double tau;              /* constant relaxation time (> 0.5 recommended) */
+    double tau_a, tau_b;     /* tau = tau_a / theta + tau_b (Sec. 3.2: 4 eta/s, 0.2546) */
+    int32_t bc[4];           /* sides x-low, x-high, y-low, y-high: rlbm_bc */
+    double theta_wall[2];    /* wall temperature of the x-low and x-high sides */
+    int32_t guess;           /* rlbm_guess */
+    const float *mlp;        /* device pointer to the MLP weights (RLBM_GUESS_MLP), else NULL */
+    void *f_a, *f_b;         /* device population buffers (ping-pong), 72*nx*ny elements each */
+    void *stream;            /* hipStream_t, NULL = default stream */
+} rlbm_params;
+
+typedef struct rlbm_init_fields {
+    /* device pointers, nx*ny doubles each.  Either n (given_z = 0) or z (given_z = 1). */
+    const double *n, *z, *theta, *ux, *uy;
+    int32_t given_z;
+} rlbm_init_fields;
+
+typedef struct rlbm_out_fields {
+    /* device pointers, nx*ny doubles each; a NULL entry is not written */
+    double *n, *eps, *theta, *z, *ux, *uy, *qx, *qy;
+} rlbm_out_fields;
+
+typedef struct rlbm_ctx rlbm_ctx;
+
+/* Validate p, build a context and write the initial state f* = f^eq(fields)
+ * into f_a (Eq. expansion-eq; for FD/BE with n given, z solves
+ * n = 2 pi theta^2 g_2(z), Eq. n-eps-eq).  On success *ctx owns a status word;
+ * on failure *ctx is NULL.  Errors: RLBM_EINVAL, RLBM_EHIP. */
+int rlbm_init(rlbm_ctx **ctx, const rlbm_params *p, const rlbm_init_fields *init);
+
+/* Enqueue nsteps >= 0 time steps (ping-pong between f_a and f_b).
+ * Errors: RLBM_EINVAL (nsteps < 0 or ctx NULL), RLBM_EHIP. */
+int rlbm_step(rlbm_ctx *ctx, int64_t nsteps);
+
+/* Fields of the current state (moments of the pre-collision populations the next
+ * step would see), written to the non-NULL device arrays of out; synchronises the
+ * stream.  Returns RLBM_EDOMAIN if the status word has bits set (then clears it). */
+int rlbm_moments(rlbm_ctx *ctx, const rlbm_out_fields *out);
+
+/* 0 if f_a holds the current state, 1 if f_b does. */
+int rlbm_state_index(const rlbm_ctx *ctx);
+
+/* Number of steps taken since rlbm_init. */
+int64_t rlbm_steps_done(const rlbm_ctx *ctx);
+
+/* Wait for the stream; RLBM_EDOMAIN if the status word is non-zero (then cleared). */
+int rlbm_sync(rlbm_ctx *ctx);
+
+/* Wait for the stream and return the status-word bits without clearing them. */
+uint32_t rlbm_status(rlbm_ctx *ctx);
+
+/* Release the context (not the caller's buffers).  NULL is a no-op. */
+void rlbm_free(rlbm_ctx *ctx);
+
+/* Text of a status code. */
+const char *rlbm_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RLBM_H */

@@ -1,0 +1,787 @@
+// rlbm.hip -- HIP (gfx950) kernels and C ABI of the d2v72 relativistic lattice
+// Boltzmann method (arXiv:1709.09073).  Interface: include/rlbm.h.
+//
+// One thread per cell.  The fused step kernel does, per cell:
+//   pull streaming with bilinear interpolation                      (Sec. 2.4)
+//   moments N^mu, T^{mu nu} through per-direction shell sums
+//   Landau frame T^a_b U^b = eps U^a: Newton on the fixed-point form
+//     u_i (T^00 - T^0j u_j) = T^i0 - T^ij u_j, started from the exact
+//     equilibrium relation |u| = 4M/(3 + sqrt(9 - 8M^2)), M = |T^0i|/T^00  (Eq. eigen-eq)
+//   n = gamma (N^0 - u.N)                                            (Eq. density-eq)
+//   (n, eps) -> (theta, z): MJ closed form; FD/BE safeguarded Newton on
+//     h(mu) = g_2^3/g_3^2 = 2n^3/(pi eps^2), mu = ln z          (Eqs. theta-eq, n-eps-eq)
+//   tau: constant or tau_a/theta + tau_b                             (Sec. 3.2)
+//   fifth-order equilibrium in separable harmonic form               (Eq. expansion-eq, App. A)
+//   Anderson-Witting relaxation f* = f + gamma(1 - v.u)/tau (f^eq - f) (Sec. 2.1)
+// and stores f* (SoA, coalesced in x).  Landau, inversion and the radial step of
+// the equilibrium run in FP64 in every precision mode; populations, streaming,
+// shell sums, angular synthesis and relaxation run in the storage precision.
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdlib>
+#include <new>
+
+#include "rlbm.h"
+#include "rlbm_tables.h"
+
+namespace {
+
+using namespace rlbm_tab;
+
+constexpr double S3H = 0.8660254037844386;   // sqrt(3)/2 rounded to FP64
+constexpr double PI_D = 3.141592653589793;
+
+// unit vectors of the 12 directions n*pi/6, exact values
+__host__ __device__ constexpr double cdir(int n) {
+    return n == 0 ? 1.0 : n == 1 ? S3H : n == 2 ? 0.5 : n == 3 ? 0.0 : n == 4 ? -0.5 : n == 5 ? -S3H
+         : n == 6 ? -1.0 : n == 7 ? -S3H : n == 8 ? -0.5 : n == 9 ? 0.0 : n == 10 ? 0.5 : S3H;
+}
+__host__ __device__ constexpr double sdir(int n) { return cdir((n + 9) % 12); }
+// cos(j*phi_n), sin(j*phi_n) from the exact table (j*n taken mod 12)
+__host__ __device__ constexpr double cjn(int j, int n) { return cdir((j * n) % 12); }
+__host__ __device__ constexpr double sjn(int j, int n) { return sdir((j * n) % 12); }
+// index of the pair (j, k), j-major, k = j..5
+__host__ __device__ constexpr int pair_index(int j, int k) { return j * 6 - (j * (j - 1)) / 2 + (k - j); }
+
+struct KArgs {
+    const void *fin;
+    void *fout;
+    int nx, ny;
+    long long plane;             // nx*ny
+    int tx, ty, ntx, ntiles, per_xcd;
+    int bc_xlo, bc_xhi, bc_ylo, bc_yhi;
+    int tau_mode;
+    double tau, tau_a, tau_b;
+    double th_wall_lo, th_wall_hi;
+    int guess;
+    const float *mlp;
+    unsigned *status;
+    // init inputs
+    const double *i_n, *i_z, *i_theta, *i_ux, *i_uy;
+    int given_z;
+    // field outputs
+    double *o_n, *o_eps, *o_theta, *o_z, *o_ux, *o_uy, *o_qx, *o_qy;
+};
+
+// ---------------------------------------------------------------- tile mapping
+// Tiles are numbered row-major; the hardware hands consecutive workgroups to the
+// 8 XCDs in turn, so workgroup b runs tile (b % 8) * per_xcd + b / 8: each XCD
+// sweeps its own contiguous band of tile rows and the one-cell halos between
+// neighbouring tiles stay inside that XCD's L2.
+__device__ __forceinline__ bool cell_of(const KArgs &a, int &x, int &y) {
+    const int b = blockIdx.x;
+    const int t = (b & 7) * a.per_xcd + (b >> 3);
+    if (t >= a.ntiles) return false;
+    const int tyi = t / a.ntx;
+    const int txi = t - tyi * a.ntx;
+    const int lx = threadIdx.x % a.tx;
+    const int ly = threadIdx.x / a.tx;
+    x = txi * a.tx + lx;
+    y = tyi * a.ty + ly;
+    return x < a.nx && y < a.ny;
+}
+
+__device__ __forceinline__ void neighbours(const KArgs &a, int x, int y, int &xl, int &xr, int &yd, int &yu) {
+    xl = x - 1;
+    xr = x + 1;
+    yd = y - 1;
+    yu = y + 1;
+    if (xl < 0) xl = (a.bc_xlo == RLBM_BC_PERIODIC) ? a.nx - 1 : 0;
+    if (xr >= a.nx) xr = (a.bc_xhi == RLBM_BC_PERIODIC) ? 0 : a.nx - 1;
+    if (yd < 0) yd = (a.bc_ylo == RLBM_BC_PERIODIC) ? a.ny - 1 : 0;
+    if (yu >= a.ny) yu = (a.bc_yhi == RLBM_BC_PERIODIC) ? 0 : a.ny - 1;
+}
+
+// ---------------------------------------------------------------- streaming
+// Pull of all 72 populations of cell (x, y).  Axis directions shift by one cell;
+// the others interpolate bilinearly from (x, y), (xb, y), (x, yb), (xb, yb) with
+// xb = x - sgn(v_x), yb = y - sgn(v_y) and weights |vx||vy|, (1-|vx|)|vy|,
+// |vx|(1-|vy|), (1-|vx|)(1-|vy|); with |v| components in {1/2, sqrt3/2} these
+// pair up into two weights wA = sqrt3/4 and wB = (1 - sqrt3/2)/2.
+template <typename S, typename R>
+__device__ __forceinline__ void pull(const S *__restrict__ fin, long long plane, int nx, int x, int y, int xl,
+                                     int xr, int yd, int yu, R (&f)[72]) {
+    const int oc = y * nx, od = yd * nx, ou = yu * nx;
+    const R wA = (R)(S3H * 0.5);
+    const R wB = (R)((1.0 - S3H) * 0.5);
+#pragma unroll
+    for (int n = 0; n < 12; ++n) {
+        const int xb = cdir(n) > 0.1 ? xl : xr;     // source column x - sgn(v_x)
+        const int rb = sdir(n) > 0.1 ? od : ou;     // source row    y - sgn(v_y)
+#pragma unroll
+        for (int s = 0; s < 6; ++s) {
+            const S *__restrict__ p = fin + (long long)(6 * n + s) * plane;
+            R v;
+            if (n == 0) v = (R)p[oc + xl];
+            else if (n == 3) v = (R)p[od + x];
+            else if (n == 6) v = (R)p[oc + xr];
+            else if (n == 9) v = (R)p[ou + x];
+            else if (n == 1 || n == 5 || n == 7 || n == 11)   // |v_x| = sqrt3/2, |v_y| = 1/2
+                v = wA * ((R)p[rb + xb] + (R)p[oc + xb]) + wB * ((R)p[rb + x] + (R)p[oc + x]);
+            else                                              // |v_x| = 1/2, |v_y| = sqrt3/2
+                v = wA * ((R)p[rb + xb] + (R)p[rb + x]) + wB * ((R)p[oc + xb] + (R)p[oc + x]);
+            f[6 * n + s] = v;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- moments
+struct Mom {
+    double N0, Nx, Ny, T00, T01, T02, T11, T12, T22;
+};
+
+template <int ST, typename R>
+__device__ __forceinline__ Mom moments(const R (&f)[72]) {
+    Mom m{0, 0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int n = 0; n < 12; ++n) {
+        R a = 0, b = 0;
+#pragma unroll
+        for (int s = 0; s < 6; ++s) {
+            const R p = (R)P_SHELL[ST][s];
+            a += f[6 * n + s] * p;
+            b += f[6 * n + s] * (p * p);
+        }
+        const double A = (double)a, B = (double)b, c = cdir(n), sn = sdir(n);
+        m.N0 += A;
+        m.Nx += A * c;
+        m.Ny += A * sn;
+        m.T00 += B;
+        m.T01 += B * c;
+        m.T02 += B * sn;
+        m.T11 += B * (c * c);
+        m.T12 += B * (c * sn);
+        m.T22 += B * (sn * sn);
+    }
+    return m;
+}
+
+// ---------------------------------------------------------------- Landau frame
+__device__ __forceinline__ void landau(const Mom &m, double &ux, double &uy, double &eps, unsigned &flags) {
+    const double inv = 1.0 / m.T00;
+    const double mx = m.T01 * inv, my = m.T02 * inv;
+    const double M2 = mx * mx + my * my;
+    const double sc = 4.0 / (3.0 + sqrt(fmax(9.0 - 8.0 * M2, 0.0)));
+    ux = sc * mx;
+    uy = sc * my;
+    bool conv = false;
+    for (int it = 0; it < 40; ++it) {
+        const double e = m.T00 - m.T01 * ux - m.T02 * uy;
+        const double Fx = m.T01 - m.T11 * ux - m.T12 * uy - e * ux;
+        const double Fy = m.T02 - m.T12 * ux - m.T22 * uy - e * uy;
+        const double a = -m.T11 + m.T01 * ux - e, b = -m.T12 + m.T02 * ux;
+        const double c = -m.T12 + m.T01 * uy, d = -m.T22 + m.T02 * uy - e;
+        const double idet = 1.0 / (a * d - b * c);
+        const double dx = (d * Fx - b * Fy) * idet, dy = (a * Fy - c * Fx) * idet;
+        ux -= dx;
+        uy -= dy;
+        if (fabs(dx) + fabs(dy) <= 1e-12) {
+            conv = true;
+            break;
+        }
+    }
+    if (!conv) flags |= RLBM_FLAG_NOCONV;
+    eps = m.T00 - m.T01 * ux - m.T02 * uy;
+}
+
+// ---------------------------------------------------------------- g_nu(z)
+// g[m] = g_m(e^mu) for m = MLO..MHI (1 <= MLO <= MHI <= 6).  Tables: Taylor in mu
+// about tabulated centres using d g_m / d mu = g_{m-1}; BE near mu = 0: series of
+// Li_m about mu = 0; far tails: the defining series.
+template <int MLO, int MHI>
+__device__ __forceinline__ void g_tail(double mu, double xi, double (&g)[7]) {
+    const double e = exp(mu);
+    double ek[5];
+    ek[1] = e;
+    ek[2] = e * e;
+    ek[3] = ek[2] * e;
+    ek[4] = ek[2] * ek[2];
+#pragma unroll
+    for (int m = MLO; m <= MHI; ++m) {
+        double s = 0, sg = 1;
+#pragma unroll
+        for (int k = 1; k <= 4; ++k) {
+            s += sg * ek[k] / pow((double)k, (double)m);
+            sg *= -xi;
+        }
+        g[m] = s;
+    }
+}
+
+template <int MLO, int MHI>
+__device__ __forceinline__ void g_table(const double (*tab)[NG], int i, double d, double (&g)[7]) {
+    double t[NT];
+    t[0] = 1.0;
+#pragma unroll
+    for (int k = 1; k < NT; ++k) t[k] = t[k - 1] * d * (1.0 / k);
+    const double *row = tab[i];
+#pragma unroll
+    for (int m = MLO; m <= MHI; ++m) {
+        double s = 0;
+#pragma unroll
+        for (int k = NT - 1; k >= 0; --k) s += row[6 - m + k] * t[k];
+        g[m] = s;
+    }
+}
+
+template <int ST, int MLO, int MHI>
+__device__ __forceinline__ void gvals(double mu, double (&g)[7], unsigned &flags) {
+    // table indices below are formed from mu: keep it finite and inside the tables' reach
+    if (!(mu > -40.0)) {
+        if (mu != mu) flags |= RLBM_FLAG_NONPOSITIVE;   // NaN
+        mu = -40.0;
+    }
+    if constexpr (ST == RLBM_BE) {
+        if (!(mu <= LOG_ZC_BE)) {
+            flags |= RLBM_FLAG_CONDENSED;
+            mu = LOG_ZC_BE;
+        }
+    }
+    if constexpr (ST == RLBM_FD) {
+        if (mu < FD_MU_MIN - 0.5 * FD_DMU) {
+            g_tail<MLO, MHI>(mu, 1.0, g);
+            return;
+        }
+        int i = (int)rint((mu - FD_MU_MIN) * (1.0 / FD_DMU));
+        if (i > FD_NC - 1) {
+            i = FD_NC - 1;
+            if (mu > FD_MU_MIN + (FD_NC - 0.5) * FD_DMU) flags |= RLBM_FLAG_RANGE;
+        }
+        g_table<MLO, MHI>(FD_TAB, i, mu - (FD_MU_MIN + i * FD_DMU), g);
+    } else {
+        if (mu < BE_MU_MIN - 0.5 * BE_DMU) {
+            g_tail<MLO, MHI>(mu, -1.0, g);
+            return;
+        }
+        if (mu < BE_MU_SPLIT - 0.5 * BE_DMU) {
+            int i = (int)rint((mu - BE_MU_MIN) * (1.0 / BE_DMU));
+            if (i > BE_NC - 1) i = BE_NC - 1;
+            g_table<MLO, MHI>(BE_TAB, i, mu - (BE_MU_MIN + i * BE_DMU), g);
+            return;
+        }
+        // Li_m(e^mu) = mu^{m-1}/(m-1)! (H_{m-1} - ln(-mu)) + sum_{k != m-1} zeta(m-k) mu^k / k!
+        const double L = log(-mu);
+        double t[BE_NZ];
+        t[0] = 1.0;
+#pragma unroll
+        for (int k = 1; k < BE_NZ; ++k) t[k] = t[k - 1] * mu * (1.0 / k);
+#pragma unroll
+        for (int m = MLO; m <= MHI; ++m) {
+            double s = 0;
+#pragma unroll
+            for (int k = BE_NZ - 1; k >= 0; --k) s += BE_ZETA[6 - m + k] * t[k];   // zeta(1) stored as 0
+            g[m] = s + t[m - 1] * (HARMONIC[m - 1] - L);
+        }
+    }
+}
+
+// Solve h(mu) = g_2^3/g_3^2 = r for mu = ln z (FD, BE), safeguarded Newton.
+template <int ST>
+__device__ __forceinline__ double invert_h(double r, double mu, unsigned &flags) {
+    double lo = -40.0, hi = (ST == RLBM_BE) ? LOG_ZC_BE : FD_MU_MIN + (FD_NC - 0.5) * FD_DMU;
+    if (ST == RLBM_BE) {
+        double g[7];
+        gvals<ST, 2, 3>(LOG_ZC_BE, g, flags);
+        if (r >= g[2] * g[2] * g[2] / (g[3] * g[3])) {
+            flags |= RLBM_FLAG_CONDENSED;
+            return LOG_ZC_BE;
+        }
+    }
+    if (!(mu > lo && mu < hi)) mu = 0.5 * (lo + hi);
+    bool conv = false;
+    for (int it = 0; it < 80; ++it) {
+        double g[7];
+        gvals<ST, 1, 3>(mu, g, flags);
+        const double q = g[2] / g[3];
+        const double h = g[2] * q * q;
+        const double F = h - r;
+        if (F > 0) hi = mu; else lo = mu;
+        const double dh = h * (3.0 * g[1] / g[2] - 2.0 * q);
+        double mn = mu - F / dh;
+        if (!(mn > lo && mn < hi)) mn = 0.5 * (lo + hi);
+        const double step = fabs(mn - mu);
+        mu = mn;
+        if (step <= 1e-12 * fmax(1.0, fabs(mu)) || hi - lo <= 4e-16 * fmax(1.0, fabs(mu))) {
+            conv = true;
+            break;
+        }
+    }
+    if (!conv) flags |= RLBM_FLAG_NOCONV;
+    return mu;
+}
+
+// Solve g_2(e^mu) = target for mu (FD, BE): fugacity from (n, theta).
+template <int ST>
+__device__ __forceinline__ double invert_g2(double target, unsigned &flags) {
+    double lo = -40.0, hi = (ST == RLBM_BE) ? LOG_ZC_BE : FD_MU_MIN + (FD_NC - 0.5) * FD_DMU;
+    double mu = (ST == RLBM_BE) ? -0.6931471805599453 : 0.0;
+    bool conv = false;
+    for (int it = 0; it < 80; ++it) {
+        double g[7];
+        gvals<ST, 1, 2>(mu, g, flags);
+        const double F = g[2] - target;
+        if (F > 0) hi = mu; else lo = mu;
+        double mn = mu - F / g[1];
+        if (!(mn > lo && mn < hi)) mn = 0.5 * (lo + hi);
+        const double step = fabs(mn - mu);
+        mu = mn;
+        if (step <= 1e-12 * fmax(1.0, fabs(mu)) || hi - lo <= 4e-16 * fmax(1.0, fabs(mu))) {
+            conv = true;
+            break;
+        }
+    }
+    if (!conv) flags |= RLBM_FLAG_NOCONV;
+    if (ST == RLBM_BE && mu >= LOG_ZC_BE) flags |= RLBM_FLAG_CONDENSED;
+    return mu;
+}
+
+// Macroscopic state of a cell: theta, z (or mu), g_1..g_6, u, gamma, n, eps.
+struct Macro {
+    double n, eps, theta, z, ux, uy, ga;
+    double g[7];
+};
+
+template <int ST>
+__device__ __forceinline__ void state_from_moments(const Mom &m, Macro &M, unsigned &flags, double mu_guess) {
+    landau(m, M.ux, M.uy, M.eps, flags);
+    const double u2 = M.ux * M.ux + M.uy * M.uy;
+    if (!(u2 < 1.0)) {
+        flags |= RLBM_FLAG_SUPERLUMINAL;
+        M.ux = M.uy = 0.0;
+    }
+    M.ga = 1.0 / sqrt(1.0 - (M.ux * M.ux + M.uy * M.uy));
+    M.n = M.ga * (m.N0 - M.ux * m.Nx - M.uy * m.Ny);
+    if (!(M.n > 0.0) || !(M.eps > 0.0)) {
+        flags |= RLBM_FLAG_NONPOSITIVE;
+        M.n = M.n > 0.0 ? M.n : 1.0;
+        M.eps = M.eps > 0.0 ? M.eps : 1.0;
+    }
+    const double r = 2.0 * M.n * M.n * M.n / (PI_D * M.eps * M.eps);
+    if constexpr (ST == RLBM_MJ) {
+        M.theta = M.eps / (2.0 * M.n);
+        M.z = r;
+#pragma unroll
+        for (int k = 1; k <= 6; ++k) M.g[k] = r;
+    } else {
+        const double mu = invert_h<ST>(r, mu_guess, flags);
+        gvals<ST, 1, 6>(mu, M.g, flags);
+        M.z = exp(mu);
+        M.theta = 0.5 * (M.g[2] / M.g[3]) * (M.eps / M.n);
+    }
+}
+
+// Fugacity and g's from (n, theta) (init, wall cells).
+template <int ST>
+__device__ __forceinline__ void state_from_n_theta(double n, double theta, Macro &M, unsigned &flags) {
+    const double target = n / (2.0 * PI_D * theta * theta);
+    M.theta = theta;
+    if constexpr (ST == RLBM_MJ) {
+        M.z = target;
+#pragma unroll
+        for (int k = 1; k <= 6; ++k) M.g[k] = target;
+    } else {
+        const double mu = invert_g2<ST>(target, flags);
+        gvals<ST, 1, 6>(mu, M.g, flags);
+        M.z = exp(mu);
+    }
+}
+
+template <int ST>
+__device__ __forceinline__ void state_from_z_theta(double z, double theta, Macro &M, unsigned &flags) {
+    M.theta = theta;
+    M.z = z;
+    if constexpr (ST == RLBM_MJ) {
+#pragma unroll
+        for (int k = 1; k <= 6; ++k) M.g[k] = z;
+    } else {
+        gvals<ST, 1, 6>(log(z), M.g, flags);
+    }
+}
+
+// ---------------------------------------------------------------- equilibrium + relaxation
+// f^eq_{s,n} = sum_j r_j(s) A_{j,n};  r_j(s) = sum_k E^(j)_{s,k} G_k P_kj(u^2) (FP64),
+// A_{j,n} = Re[(u_x + i u_y)^j e^{-i j phi_n}], G_k = k! g_{k+1} theta^{k+1} gamma^k.
+// If COLLIDE: f <- f + omega_n (f^eq - f), omega_n = gamma (1 - v_n.u) / tau; else f <- f^eq.
+template <int ST, bool COLLIDE, typename R>
+__device__ __forceinline__ void equilibrium_relax(const Macro &M, double tau, R (&f)[72]) {
+    const double u2 = M.ux * M.ux + M.uy * M.uy;
+    double G[6];
+    {
+        double th = M.theta, gk = 1.0, fact = 1.0;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            if (k > 0) fact *= (double)k;
+            G[k] = fact * M.g[k + 1] * th * gk;
+            th *= M.theta;
+            gk *= M.ga;
+        }
+    }
+    double h[21];
+#pragma unroll
+    for (int j = 0; j < 6; ++j)
+#pragma unroll
+        for (int k = j; k < 6; ++k) {
+            const int pi = pair_index(j, k);
+            h[pi] = G[k] * (PKJ[pi][0] + u2 * (PKJ[pi][1] + u2 * PKJ[pi][2]));
+        }
+    // harmonics (u_x + i u_y)^j
+    R C[6], S[6];
+    {
+        double c = 1.0, s = 0.0;
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            C[j] = (R)c;
+            S[j] = (R)s;
+            const double cn = c * M.ux - s * M.uy;
+            s = c * M.uy + s * M.ux;
+            c = cn;
+        }
+    }
+    // A_{j,n} for n = 0..5 (n + 6 follows from A_{j,n+6} = (-1)^j A_{j,n})
+    R A[6][6];
+#pragma unroll
+    for (int n = 0; n < 6; ++n) {
+        A[0][n] = (R)1;
+#pragma unroll
+        for (int j = 1; j < 6; ++j) A[j][n] = C[j] * (R)cjn(j, n) + S[j] * (R)sjn(j, n);
+    }
+    R om[12];
+    if constexpr (COLLIDE) {
+        const R gt = (R)(M.ga / tau);
+        const R ux = (R)M.ux, uy = (R)M.uy;
+#pragma unroll
+        for (int n = 0; n < 6; ++n) {
+            const R vu = ux * (R)cdir(n) + uy * (R)sdir(n);
+            om[n] = gt - gt * vu;
+            om[n + 6] = gt + gt * vu;
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+        R r[6];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            double acc = 0.0;
+#pragma unroll
+            for (int k = j; k < 6; ++k) acc += EMAT[ST][pair_index(j, k)][s] * h[pair_index(j, k)];
+            r[j] = (R)acc;
+        }
+#pragma unroll
+        for (int n = 0; n < 6; ++n) {
+            const R ev = r[0] + r[2] * A[2][n] + r[4] * A[4][n];
+            const R od = r[1] * A[1][n] + r[3] * A[3][n] + r[5] * A[5][n];
+            const R fe0 = ev + od, fe1 = ev - od;
+            R &a = f[6 * n + s];
+            R &b = f[6 * (n + 6) + s];
+            if constexpr (COLLIDE) {
+                a = a + om[n] * (fe0 - a);
+                b = b + om[n + 6] * (fe1 - b);
+            } else {
+                a = fe0;
+                b = fe1;
+            }
+        }
+    }
+}
+
+template <typename S, typename R>
+__device__ __forceinline__ void store(S *__restrict__ fout, long long plane, int off, const R (&f)[72]) {
+#pragma unroll
+    for (int q = 0; q < 72; ++q) fout[(long long)q * plane + off] = (S)f[q];
+}
+
+__device__ __forceinline__ void report(unsigned *status, unsigned flags) {
+    if (flags) atomicOr(status, flags);
+}
+
+// ---------------------------------------------------------------- kernels
+template <int ST, typename S, typename R>
+__global__ __launch_bounds__(256) void k_step(KArgs a) {
+    int x, y;
+    if (!cell_of(a, x, y)) return;
+    unsigned flags = 0;
+    const bool wall_lo = (a.bc_xlo == RLBM_BC_WALL_T) && x == 0;
+    const bool wall_hi = (a.bc_xhi == RLBM_BC_WALL_T) && x == a.nx - 1;
+    const int xe = wall_lo ? 1 : (wall_hi ? a.nx - 2 : x);   // wall cells read their fluid neighbour
+    int xl, xr, yd, yu;
+    neighbours(a, xe, y, xl, xr, yd, yu);
+    R f[72];
+    pull<S, R>((const S *)a.fin, a.plane, a.nx, xe, y, xl, xr, yd, yu, f);
+    const Mom m = moments<ST, R>(f);
+    Macro M;
+    const double mu0 = (ST == RLBM_BE) ? -0.6931471805599453 : 0.0;
+    state_from_moments<ST>(m, M, flags, mu0);
+    if (wall_lo || wall_hi) {
+        // zeroth-order extrapolation of n and u, fixed wall temperature
+        const double n = M.n;
+        state_from_n_theta<ST>(n, wall_lo ? a.th_wall_lo : a.th_wall_hi, M, flags);
+        equilibrium_relax<ST, false, R>(M, 1.0, f);
+    } else {
+        const double tau = (a.tau_mode == RLBM_TAU_CONST) ? a.tau : a.tau_a / M.theta + a.tau_b;
+        equilibrium_relax<ST, true, R>(M, tau, f);
+    }
+    store<S, R>((S *)a.fout, a.plane, y * a.nx + x, f);
+    report(a.status, flags);
+}
+
+template <int ST, typename S, typename R>
+__global__ __launch_bounds__(256) void k_moments(KArgs a) {
+    int x, y;
+    if (!cell_of(a, x, y)) return;
+    unsigned flags = 0;
+    int xl, xr, yd, yu;
+    neighbours(a, x, y, xl, xr, yd, yu);
+    R f[72];
+    pull<S, R>((const S *)a.fin, a.plane, a.nx, x, y, xl, xr, yd, yu, f);
+    const Mom m = moments<ST, R>(f);
+    Macro M;
+    const double mu0 = (ST == RLBM_BE) ? -0.6931471805599453 : 0.0;
+    state_from_moments<ST>(m, M, flags, mu0);
+    const int off = y * a.nx + x;
+    const double hE = 3.0 * M.theta * M.g[3] / M.g[2];
+    if (a.o_n) a.o_n[off] = M.n;
+    if (a.o_eps) a.o_eps[off] = M.eps;
+    if (a.o_theta) a.o_theta[off] = M.theta;
+    if (a.o_z) a.o_z[off] = M.z;
+    if (a.o_ux) a.o_ux[off] = M.ux;
+    if (a.o_uy) a.o_uy[off] = M.uy;
+    if (a.o_qx) a.o_qx[off] = hE * (M.n * M.ga * M.ux - m.Nx);
+    if (a.o_qy) a.o_qy[off] = hE * (M.n * M.ga * M.uy - m.Ny);
+    report(a.status, flags);
+}
+
+template <int ST, typename S, typename R>
+__global__ __launch_bounds__(256) void k_init(KArgs a) {
+    int x, y;
+    if (!cell_of(a, x, y)) return;
+    unsigned flags = 0;
+    const int off = y * a.nx + x;
+    Macro M;
+    M.ux = a.i_ux[off];
+    M.uy = a.i_uy[off];
+    const double u2 = M.ux * M.ux + M.uy * M.uy;
+    if (!(u2 < 1.0)) {
+        flags |= RLBM_FLAG_SUPERLUMINAL;
+        M.ux = M.uy = 0.0;
+    }
+    M.ga = 1.0 / sqrt(1.0 - (M.ux * M.ux + M.uy * M.uy));
+    const double th = a.i_theta[off];
+    if (a.given_z) state_from_z_theta<ST>(a.i_z[off], th, M, flags);
+    else state_from_n_theta<ST>(a.i_n[off], th, M, flags);
+    R f[72];
+    equilibrium_relax<ST, false, R>(M, 1.0, f);
+    store<S, R>((S *)a.fout, a.plane, off, f);
+    report(a.status, flags);
+}
+
+// ---------------------------------------------------------------- host side
+using KFn = void (*)(KArgs);
+
+template <int ST>
+struct Kern {
+    static KFn step(int prec) { return prec == RLBM_FP64 ? k_step<ST, double, double> : k_step<ST, float, float>; }
+    static KFn mom(int prec) { return prec == RLBM_FP64 ? k_moments<ST, double, double> : k_moments<ST, float, float>; }
+    static KFn init(int prec) { return prec == RLBM_FP64 ? k_init<ST, double, double> : k_init<ST, float, float>; }
+};
+
+KFn pick(int which, int st, int prec) {
+    switch (st) {
+        case RLBM_MJ: return which == 0 ? Kern<RLBM_MJ>::step(prec) : which == 1 ? Kern<RLBM_MJ>::mom(prec) : Kern<RLBM_MJ>::init(prec);
+        case RLBM_FD: return which == 0 ? Kern<RLBM_FD>::step(prec) : which == 1 ? Kern<RLBM_FD>::mom(prec) : Kern<RLBM_FD>::init(prec);
+        default: return which == 0 ? Kern<RLBM_BE>::step(prec) : which == 1 ? Kern<RLBM_BE>::mom(prec) : Kern<RLBM_BE>::init(prec);
+    }
+}
+
+}  // namespace
+
+struct rlbm_ctx {
+    rlbm_params p;
+    KArgs base;
+    hipStream_t stream;
+    unsigned *status;     // device status word
+    int cur;              // 0: f_a holds the state, 1: f_b
+    int64_t steps;
+    dim3 grid, block;
+};
+
+namespace {
+
+int validate(const rlbm_params *p) {
+    if (!p) return RLBM_EINVAL;
+    if (p->nx < 2 || p->ny < 2) return RLBM_EINVAL;
+    if ((long long)p->nx * p->ny > (1LL << 31) - 1) return RLBM_EINVAL;
+    if (p->stats < RLBM_MJ || p->stats > RLBM_BE) return RLBM_EINVAL;
+    if (p->order != 5) return (p->order >= 2 && p->order <= 4) ? RLBM_ENOTIMPL : RLBM_EINVAL;
+    if (p->precision != RLBM_FP64 && p->precision != RLBM_FP32) return RLBM_EINVAL;
+    if (p->tau_mode == RLBM_TAU_CONST) {
+        if (!(p->tau > 0.0)) return RLBM_EINVAL;
+    } else if (p->tau_mode == RLBM_TAU_INV_THETA) {
+        if (!(p->tau_a >= 0.0) || !(p->tau_b > 0.0)) return RLBM_EINVAL;
+    } else {
+        return RLBM_EINVAL;
+    }
+    for (int i = 0; i < 4; ++i)
+        if (p->bc[i] < RLBM_BC_PERIODIC || p->bc[i] > RLBM_BC_WALL_T) return RLBM_EINVAL;
+    if ((p->bc[0] == RLBM_BC_PERIODIC) != (p->bc[1] == RLBM_BC_PERIODIC)) return RLBM_EINVAL;
+    if ((p->bc[2] == RLBM_BC_PERIODIC) != (p->bc[3] == RLBM_BC_PERIODIC)) return RLBM_EINVAL;
+    if (p->bc[2] == RLBM_BC_WALL_T || p->bc[3] == RLBM_BC_WALL_T) return RLBM_EINVAL;
+    if ((p->bc[0] == RLBM_BC_WALL_T || p->bc[1] == RLBM_BC_WALL_T) && p->nx < 4) return RLBM_EINVAL;
+    for (int i = 0; i < 2; ++i)
+        if (p->bc[i] == RLBM_BC_WALL_T && !(p->theta_wall[i] > 0.0)) return RLBM_EINVAL;
+    if (p->guess != RLBM_GUESS_FIXED) return RLBM_ENOTIMPL;
+    if (!p->f_a || !p->f_b || p->f_a == p->f_b) return RLBM_EINVAL;
+    return RLBM_OK;
+}
+
+void tile_shape(int nx, int ny, int &tx, int &ty) {
+    ty = ny >= 4 ? 4 : (ny >= 2 ? 2 : 1);
+    tx = 256 / ty;
+    (void)nx;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rlbm_init(rlbm_ctx **out, const rlbm_params *p, const rlbm_init_fields *init) {
+    if (!out) return RLBM_EINVAL;
+    *out = nullptr;
+    int rc = validate(p);
+    if (rc) return rc;
+    if (!init || !init->theta || !init->ux || !init->uy || (init->given_z ? !init->z : !init->n)) return RLBM_EINVAL;
+    rlbm_ctx *c = new (std::nothrow) rlbm_ctx();
+    if (!c) return RLBM_EHIP;
+    c->p = *p;
+    c->stream = (hipStream_t)p->stream;
+    if (hipMalloc(&c->status, sizeof(unsigned)) != hipSuccess) {
+        delete c;
+        return RLBM_EHIP;
+    }
+    if (hipMemsetAsync(c->status, 0, sizeof(unsigned), c->stream) != hipSuccess) {
+        hipFree(c->status);
+        delete c;
+        return RLBM_EHIP;
+    }
+    KArgs &a = c->base;
+    a = KArgs{};
+    a.nx = p->nx;
+    a.ny = p->ny;
+    a.plane = (long long)p->nx * p->ny;
+    tile_shape(p->nx, p->ny, a.tx, a.ty);
+    a.ntx = (p->nx + a.tx - 1) / a.tx;
+    a.ntiles = a.ntx * ((p->ny + a.ty - 1) / a.ty);
+    a.per_xcd = (a.ntiles + 7) / 8;
+    a.bc_xlo = p->bc[0];
+    a.bc_xhi = p->bc[1];
+    a.bc_ylo = p->bc[2];
+    a.bc_yhi = p->bc[3];
+    a.tau_mode = p->tau_mode;
+    a.tau = p->tau;
+    a.tau_a = p->tau_a;
+    a.tau_b = p->tau_b;
+    a.th_wall_lo = p->theta_wall[0];
+    a.th_wall_hi = p->theta_wall[1];
+    a.guess = p->guess;
+    a.mlp = p->mlp;
+    a.status = c->status;
+    c->grid = dim3(8 * a.per_xcd);
+    c->block = dim3(256);
+    c->cur = 0;
+    c->steps = 0;
+    KArgs ia = a;
+    ia.fout = p->f_a;
+    ia.i_n = init->n;
+    ia.i_z = init->z;
+    ia.i_theta = init->theta;
+    ia.i_ux = init->ux;
+    ia.i_uy = init->uy;
+    ia.given_z = init->given_z;
+    hipLaunchKernelGGL(pick(2, p->stats, p->precision), c->grid, c->block, 0, c->stream, ia);
+    if (hipGetLastError() != hipSuccess) {
+        hipFree(c->status);
+        delete c;
+        return RLBM_EHIP;
+    }
+    *out = c;
+    return RLBM_OK;
+}
+
+int rlbm_step(rlbm_ctx *c, int64_t nsteps) {
+    if (!c || nsteps < 0) return RLBM_EINVAL;
+    KFn fn = pick(0, c->p.stats, c->p.precision);
+    for (int64_t i = 0; i < nsteps; ++i) {
+        KArgs a = c->base;
+        a.fin = c->cur ? c->p.f_b : c->p.f_a;
+        a.fout = c->cur ? c->p.f_a : c->p.f_b;
+        hipLaunchKernelGGL(fn, c->grid, c->block, 0, c->stream, a);
+        c->cur ^= 1;
+        c->steps++;
+    }
+    return hipGetLastError() == hipSuccess ? RLBM_OK : RLBM_EHIP;
+}
+
+int rlbm_moments(rlbm_ctx *c, const rlbm_out_fields *o) {
+    if (!c || !o) return RLBM_EINVAL;
+    KArgs a = c->base;
+    a.fin = c->cur ? c->p.f_b : c->p.f_a;
+    a.o_n = o->n;
+    a.o_eps = o->eps;
+    a.o_theta = o->theta;
+    a.o_z = o->z;
+    a.o_ux = o->ux;
+    a.o_uy = o->uy;
+    a.o_qx = o->qx;
+    a.o_qy = o->qy;
+    hipLaunchKernelGGL(pick(1, c->p.stats, c->p.precision), c->grid, c->block, 0, c->stream, a);
+    if (hipGetLastError() != hipSuccess) return RLBM_EHIP;
+    return rlbm_sync(c);
+}
+
+int rlbm_state_index(const rlbm_ctx *c) { return c ? c->cur : -1; }
+
+int64_t rlbm_steps_done(const rlbm_ctx *c) { return c ? c->steps : -1; }
+
+uint32_t rlbm_status(rlbm_ctx *c) {
+    if (!c) return 0;
+    unsigned h = 0;
+    if (hipMemcpyAsync(&h, c->status, sizeof(unsigned), hipMemcpyDeviceToHost, c->stream) != hipSuccess) return 0xffffffffu;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return 0xffffffffu;
+    return h;
+}
+
+int rlbm_sync(rlbm_ctx *c) {
+    if (!c) return RLBM_EINVAL;
+    unsigned h = 0;
+    if (hipMemcpyAsync(&h, c->status, sizeof(unsigned), hipMemcpyDeviceToHost, c->stream) != hipSuccess) return RLBM_EHIP;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return RLBM_EHIP;
+    if (h) {
+        unsigned zero = 0;
+        if (hipMemcpy(c->status, &zero, sizeof(unsigned), hipMemcpyHostToDevice) != hipSuccess) return RLBM_EHIP;
+        return RLBM_EDOMAIN;
+    }
+    return RLBM_OK;
+}
+
+void rlbm_free(rlbm_ctx *c) {
+    if (!c) return;
+    hipStreamSynchronize(c->stream);
+    hipFree(c->status);
+    delete c;
+}
+
+const char *rlbm_strerror(int code) {
+    switch (code) {
+        case RLBM_OK: return "ok";
+        case RLBM_EINVAL: return "invalid argument";
+        case RLBM_EDOMAIN: return "state outside the method's domain (see rlbm_status bits)";
+        case RLBM_EHIP: return "HIP runtime error";
+        case RLBM_ENONFINITE: return "non-finite field";
+        case RLBM_ENOTIMPL: return "not supported by this build";
+        default: return "unknown status code";
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,157 @@
+"""Thin ctypes binding of librlbm.so (include/rlbm.h): argument marshalling only.
+
+Every step of the method runs in the HIP kernels; PyTorch provides the device
+buffers and the stream.  Importing this module loads the library and fails loudly
+if it has not been built (python -m paper_1709_09073_amd.build).
+"""
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librlbm.so")
+
+RLBM_OK, RLBM_EINVAL, RLBM_EDOMAIN, RLBM_EHIP, RLBM_ENONFINITE, RLBM_ENOTIMPL = 0, -1, -2, -3, -4, -5
+STATS = {"MJ": 0, "FD": 1, "BE": 2}
+PRECISION = {"fp64": 0, "fp32": 1}
+TAU_MODE = {"const": 0, "theta": 1}
+BC = {"periodic": 0, "open": 1, "wall": 2}
+GUESS = {"fixed": 0, "mlp": 1}
+DTYPE = {"fp64": torch.float64, "fp32": torch.float32}
+FIELD_NAMES = ("n", "eps", "theta", "z", "ux", "uy", "qx", "qy")
+
+FLAG_NONPOSITIVE, FLAG_SUPERLUMINAL, FLAG_CONDENSED, FLAG_RANGE, FLAG_NOCONV = 0x1, 0x2, 0x4, 0x8, 0x10
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("stats", ctypes.c_int32),
+                ("order", ctypes.c_int32), ("precision", ctypes.c_int32), ("tau_mode", ctypes.c_int32),
+                ("tau", ctypes.c_double), ("tau_a", ctypes.c_double), ("tau_b", ctypes.c_double),
+                ("bc", ctypes.c_int32 * 4), ("theta_wall", ctypes.c_double * 2), ("guess", ctypes.c_int32),
+                ("mlp", ctypes.c_void_p), ("f_a", ctypes.c_void_p), ("f_b", ctypes.c_void_p),
+                ("stream", ctypes.c_void_p)]
+
+
+class InitFields(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_void_p), ("z", ctypes.c_void_p), ("theta", ctypes.c_void_p),
+                ("ux", ctypes.c_void_p), ("uy", ctypes.c_void_p), ("given_z", ctypes.c_int32)]
+
+
+class OutFields(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_void_p) for k in FIELD_NAMES]
+
+
+class RlbmError(RuntimeError):
+    def __init__(self, code, what=""):
+        self.code = code
+        super().__init__(f"{what}: {lib().rlbm_strerror(code).decode()} ({code})")
+
+
+_LIB = None
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1709_09073_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        L.rlbm_init.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(Params), ctypes.POINTER(InitFields)]
+        L.rlbm_step.argtypes = [ctypes.c_void_p, ctypes.c_int64]
+        L.rlbm_moments.argtypes = [ctypes.c_void_p, ctypes.POINTER(OutFields)]
+        L.rlbm_state_index.argtypes = [ctypes.c_void_p]
+        L.rlbm_steps_done.argtypes = [ctypes.c_void_p]
+        L.rlbm_steps_done.restype = ctypes.c_int64
+        L.rlbm_sync.argtypes = [ctypes.c_void_p]
+        L.rlbm_status.argtypes = [ctypes.c_void_p]
+        L.rlbm_status.restype = ctypes.c_uint32
+        L.rlbm_free.argtypes = [ctypes.c_void_p]
+        L.rlbm_free.restype = None
+        L.rlbm_strerror.argtypes = [ctypes.c_int]
+        L.rlbm_strerror.restype = ctypes.c_char_p
+        _LIB = L
+    return _LIB
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _check(code, what):
+    if code != RLBM_OK:
+        raise RlbmError(code, what)
+
+
+class Sim:
+    """One grid: owns two population tensors (ping-pong) on the current CUDA/HIP device.
+
+    params: dict with keys nx, ny, stats ('MJ'|'FD'|'BE'), precision ('fp64'|'fp32'),
+    tau_mode ('const'|'theta'), tau, tau_a, tau_b, bc (xlo, xhi, ylo, yhi names),
+    theta_wall (xlo, xhi), guess ('fixed'|'mlp').  init: dict of (ny, nx) float64
+    CUDA tensors theta, ux, uy and either n or z.
+    """
+
+    def __init__(self, params, init, device="cuda", stream=None):
+        L = lib()
+        self.params = dict(params)
+        nx, ny = int(params["nx"]), int(params["ny"])
+        prec = params.get("precision", "fp64")
+        self.nx, self.ny, self.precision = nx, ny, prec
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        self.f = [torch.empty((72, ny, nx), dtype=DTYPE[prec], device=device) for _ in range(2)]
+        bc = params.get("bc", ("periodic",) * 4)
+        tw = params.get("theta_wall", (1.0, 1.0))
+        p = Params(nx=nx, ny=ny, stats=STATS[params.get("stats", "MJ")], order=int(params.get("order", 5)),
+                   precision=PRECISION[prec], tau_mode=TAU_MODE[params.get("tau_mode", "const")],
+                   tau=float(params.get("tau", 1.0)), tau_a=float(params.get("tau_a", 2.0)),
+                   tau_b=float(params.get("tau_b", 0.2546)), guess=GUESS[params.get("guess", "fixed")],
+                   mlp=_ptr(params.get("mlp")), f_a=_ptr(self.f[0]), f_b=_ptr(self.f[1]),
+                   stream=ctypes.c_void_p(self.stream.cuda_stream))
+        p.bc[:] = [BC[b] for b in bc]
+        p.theta_wall[:] = [float(t) for t in tw]
+        self._init_tensors = {k: v.contiguous().to(device=device, dtype=torch.float64) for k, v in init.items()}
+        it = self._init_tensors
+        given_z = "z" in it
+        fi = InitFields(n=_ptr(it.get("n")), z=_ptr(it.get("z")), theta=_ptr(it["theta"]), ux=_ptr(it["ux"]),
+                        uy=_ptr(it["uy"]), given_z=int(given_z))
+        self._p = p
+        ctx = ctypes.c_void_p()
+        _check(L.rlbm_init(ctypes.byref(ctx), ctypes.byref(p), ctypes.byref(fi)), "rlbm_init")
+        self.ctx = ctx
+
+    def step(self, nsteps=1):
+        _check(lib().rlbm_step(self.ctx, int(nsteps)), "rlbm_step")
+
+    def state(self):
+        """The tensor (72, ny, nx) holding the current post-collision populations."""
+        return self.f[lib().rlbm_state_index(self.ctx)]
+
+    @property
+    def steps_done(self):
+        return lib().rlbm_steps_done(self.ctx)
+
+    def fields(self, names=FIELD_NAMES, check=True):
+        out = {k: torch.empty((self.ny, self.nx), dtype=torch.float64, device=self.f[0].device) for k in names}
+        of = OutFields(**{k: _ptr(out.get(k)) for k in FIELD_NAMES})
+        rc = lib().rlbm_moments(self.ctx, ctypes.byref(of))
+        if check:
+            _check(rc, "rlbm_moments")
+        return out
+
+    def sync(self):
+        _check(lib().rlbm_sync(self.ctx), "rlbm_sync")
+
+    def status(self):
+        return lib().rlbm_status(self.ctx)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            lib().rlbm_free(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,158 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+FP64 storage: fields n, eps, theta, z, u to 1e-12 relative (max norm); the heat
+flux, a cancellation moment, to 1e-11 of its max norm; populations per radial
+shell relative to that shell's max (the outer shells carry the rounding of the
+ill-conditioned radial projection: see the oracle's brute-force comparison).
+FP32 storage: the tolerances derived in the design doc (populations stored with
+2^-24 relative rounding; a few units of it per step).
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import lattice as L
+
+pytestmark = pytest.mark.gpu
+
+SHELL_TOL_FP64 = (2e-13, 2e-13, 2e-13, 1e-12, 5e-12, 5e-11)
+FIELD_TOL_FP64 = dict(n=1e-12, eps=1e-12, theta=1e-12, z=1e-12, ux=1e-12, uy=1e-12, qx=1e-11, qy=1e-11)
+FIELD_TOL_FP32 = dict(n=2e-6, eps=2e-6, theta=2e-6, z=5e-6, ux=2e-5, uy=2e-5, qx=2e-3, qy=2e-3)
+
+
+@pytest.fixture(scope="module")
+def rl():
+    from paper_1709_09073_amd import rlbm
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return rlbm
+
+
+def _oracle_params(params, stats):
+    bcmap = dict(zip(("xlo", "xhi", "ylo", "yhi"), params.get("bc", ("periodic",) * 4)))
+    tw = params.get("theta_wall", (1.0, 1.0))
+    return L.Params(stats=stats, nx=params["nx"], ny=params["ny"], tau_mode=params.get("tau_mode", "const"),
+                    tau=params.get("tau", 1.0), tau_a=params.get("tau_a", 2.0), tau_b=params.get("tau_b", 0.2546),
+                    bc=bcmap, theta_wall=dict(xlo=tw[0], xhi=tw[1]))
+
+
+def _oracle_init(op, fields):
+    f = {k: v.cpu().numpy() for k, v in fields.items()}
+    return L.init_state(op, f["theta"], f["ux"], f["uy"], n=f.get("n"), z=f.get("z"))
+
+
+def _compare_fields(a, b, tol, ctx):
+    for k, t in tol.items():
+        ref = b[k]
+        err = np.abs(a[k] - ref).max() / max(np.abs(ref).max(), 1e-300)
+        assert err <= t, f"{ctx}: field {k} rel err {err:.3e} > {t:.1e}"
+
+
+def _compare_pops(a, b, tols, ctx):
+    for k, t in enumerate(tols):
+        sl = slice(k, 72, 6)
+        err = np.abs(a[sl] - b[sl]).max() / np.abs(b[sl]).max()
+        assert err <= t, f"{ctx}: shell {k} rel err {err:.3e} > {t:.1e}"
+
+
+def _run(rl, stats, precision, params, fields, nsteps):
+    params = dict(params, stats=stats, precision=precision)
+    print(f"[parity] {stats} {precision} {params['nx']}x{params['ny']} bc={params.get('bc')} steps={nsteps}", flush=True)
+    sim = rl.Sim(params, {k: v.cuda() for k, v in fields.items()})
+    sim.step(nsteps)
+    pops = sim.state().double().cpu().numpy()
+    flds = {k: v.cpu().numpy() for k, v in sim.fields().items()}
+    sim.close()
+    op = _oracle_params(params, stats)
+    f = _oracle_init(op, fields)
+    for _ in range(nsteps):
+        f, _ = L.step(f, op)
+    return pops, flds, f, L.fields(f, op)
+
+
+CASES = [
+    # stats, nx, ny, steps, bc, tau_mode
+    ("MJ", 70, 13, 6, ("periodic",) * 4, "const"),
+    ("MJ", 67, 9, 4, ("open",) * 4, "theta"),
+    ("FD", 70, 13, 3, ("periodic",) * 4, "const"),
+    ("FD", 66, 7, 3, ("open", "open", "periodic", "periodic"), "theta"),
+    ("BE", 70, 13, 3, ("open",) * 4, "const"),
+    ("BE", 65, 6, 2, ("periodic",) * 4, "theta"),
+]
+
+
+@pytest.mark.parametrize("stats,nx,ny,nsteps,bc,tau_mode", CASES)
+def test_fp64_parity(rl, stats, nx, ny, nsteps, bc, tau_mode):
+    fields = workloads.smooth_random(nx, ny, seed=nx * ny, stats=stats)
+    params = dict(nx=nx, ny=ny, bc=bc, tau_mode=tau_mode, tau=0.85, tau_a=0.6, tau_b=0.6)
+    pops, flds, fo, flo = _run(rl, stats, "fp64", params, fields, nsteps)
+    ctx = f"{stats} fp64 {nx}x{ny} {bc[0]}"
+    _compare_pops(pops, fo, SHELL_TOL_FP64, ctx)
+    _compare_fields(flds, flo, FIELD_TOL_FP64, ctx)
+
+
+@pytest.mark.parametrize("stats", ["MJ", "FD", "BE"])
+def test_fp64_init_parity(rl, stats):
+    fields = workloads.smooth_random(33, 5, seed=5, stats=stats)
+    params = dict(nx=33, ny=5)
+    pops, flds, fo, flo = _run(rl, stats, "fp64", params, fields, 0)
+    _compare_pops(pops, fo, SHELL_TOL_FP64, f"{stats} init")
+    _compare_fields(flds, flo, FIELD_TOL_FP64, f"{stats} init")
+
+
+@pytest.mark.parametrize("stats", ["MJ", "FD", "BE"])
+def test_fp64_walls(rl, stats):
+    params, fields = workloads.fourier(nx=40, ny=4, dT=0.05, tau=0.9)
+    pops, flds, fo, flo = _run(rl, stats, "fp64", params, fields, 4)
+    _compare_pops(pops, fo, SHELL_TOL_FP64, f"{stats} walls")
+    _compare_fields(flds, flo, dict(FIELD_TOL_FP64, qx=1e-10, qy=1e-9), f"{stats} walls")
+
+
+@pytest.mark.parametrize("stats,nsteps", [("MJ", 8), ("FD", 3), ("BE", 3)])
+def test_fp32_parity(rl, stats, nsteps):
+    fields = workloads.smooth_random(70, 13, seed=3, stats=stats)
+    params = dict(nx=70, ny=13, bc=("periodic",) * 4, tau=0.9)
+    pops, flds, fo, flo = _run(rl, stats, "fp32", params, fields, nsteps)
+    _compare_fields(flds, flo, FIELD_TOL_FP32, f"{stats} fp32")
+
+
+def test_riemann_fp64_full_config(rl):
+    """Shock tube MJ, 1024 x 4, FP64, tau = 0.9, 500 steps: the small configuration."""
+    params, fields = workloads.riemann(nx=1024, ny=4, tau=0.9)
+    pops, flds, fo, flo = _run(rl, "MJ", "fp64", params, fields, 500)
+    _compare_fields(flds, flo, dict(FIELD_TOL_FP64, qx=1e-10, qy=1e-10), "riemann")
+
+
+def test_minimal_grid(rl):
+    fields = workloads.smooth_random(2, 2, seed=9, stats="MJ", amp_u=0.05)
+    params = dict(nx=2, ny=2)
+    pops, flds, fo, flo = _run(rl, "MJ", "fp64", params, fields, 3)
+    _compare_fields(flds, flo, FIELD_TOL_FP64, "2x2")
+
+
+def test_domain_flag_be_condensation(rl):
+    """A BE state beyond the condensation bound is clamped and reported."""
+    nx, ny = 16, 4
+    th = torch.ones((ny, nx), dtype=torch.float64)
+    # n far above 2 pi theta^2 g_2(z_c) = 2 pi zeta(2)(1 - ...) ~ 10.3
+    fields = dict(n=torch.full((ny, nx), 50.0, dtype=torch.float64), theta=th,
+                  ux=torch.zeros_like(th), uy=torch.zeros_like(th))
+    sim = rl.Sim(dict(nx=nx, ny=ny, stats="BE", precision="fp64"), {k: v.cuda() for k, v in fields.items()})
+    assert sim.status() & rl.FLAG_CONDENSED
+    with pytest.raises(rl.RlbmError):
+        sim.sync()
+    assert sim.status() == 0
+    sim.close()
+
+
+def test_deterministic(rl):
+    fields = workloads.smooth_random(130, 17, seed=1, stats="FD")
+    params = dict(nx=130, ny=17, stats="FD", precision="fp32")
+    outs = []
+    for _ in range(2):
+        sim = rl.Sim(params, {k: v.cuda() for k, v in fields.items()})
+        sim.step(5)
+        outs.append(sim.state().cpu().clone())
+        sim.close()
+    assert torch.equal(outs[0], outs[1])

@@ -1,0 +1,94 @@
+"""Host-side checks of librlbm.so that need no GPU: it loads, exports every symbol
+include/rlbm.h declares, and rejects invalid arguments before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def rl():
+    from paper_1709_09073_amd import rlbm
+    rlbm.lib()
+    return rlbm
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "rlbm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(rlbm_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol(rl):
+    names = declared_functions()
+    assert "rlbm_init" in names and "rlbm_step" in names and "rlbm_moments" in names
+    L = rl.lib()
+    for nm in names:
+        assert hasattr(L, nm), nm
+
+
+def test_strerror(rl):
+    L = rl.lib()
+    for code in (0, -1, -2, -3, -4, -5, -99):
+        assert isinstance(L.rlbm_strerror(code), bytes)
+
+
+def _params(**kw):
+    from paper_1709_09073_amd import rlbm
+    p = rlbm.Params(nx=16, ny=8, stats=0, order=5, precision=0, tau_mode=0, tau=1.0, tau_a=2.0, tau_b=0.25,
+                    guess=0, mlp=None, f_a=ctypes.c_void_p(0x1000), f_b=ctypes.c_void_p(0x2000), stream=None)
+    p.bc[:] = [0, 0, 0, 0]
+    p.theta_wall[:] = [1.0, 1.0]
+    for k, v in kw.items():
+        if k == "bc":
+            p.bc[:] = v
+        else:
+            setattr(p, k, v)
+    return p
+
+
+INVALID = [
+    dict(nx=1), dict(ny=0), dict(stats=3), dict(order=7), dict(precision=5), dict(tau=0.0),
+    dict(tau_mode=1, tau_b=0.0), dict(tau_mode=2), dict(bc=[0, 1, 0, 0]), dict(bc=[0, 0, 2, 2]),
+    dict(bc=[2, 2, 0, 0], nx=3), dict(f_a=ctypes.c_void_p(0)), dict(f_b=ctypes.c_void_p(0x1000)),
+]
+
+
+@pytest.mark.parametrize("kw", INVALID)
+def test_invalid_params_rejected(rl, kw):
+    L = rl.lib()
+    p = _params(**kw)
+    fi = rl.InitFields(n=ctypes.c_void_p(0x10), z=None, theta=ctypes.c_void_p(0x10), ux=ctypes.c_void_p(0x10),
+                       uy=ctypes.c_void_p(0x10), given_z=0)
+    ctx = ctypes.c_void_p()
+    assert L.rlbm_init(ctypes.byref(ctx), ctypes.byref(p), ctypes.byref(fi)) == rl.RLBM_EINVAL
+    assert not ctx.value
+
+
+def test_lower_orders_not_in_this_build(rl):
+    L = rl.lib()
+    p = _params(order=3)
+    fi = rl.InitFields(n=ctypes.c_void_p(0x10), z=None, theta=ctypes.c_void_p(0x10), ux=ctypes.c_void_p(0x10),
+                       uy=ctypes.c_void_p(0x10), given_z=0)
+    ctx = ctypes.c_void_p()
+    assert L.rlbm_init(ctypes.byref(ctx), ctypes.byref(p), ctypes.byref(fi)) == rl.RLBM_ENOTIMPL
+
+
+def test_missing_init_fields_rejected(rl):
+    L = rl.lib()
+    p = _params()
+    fi = rl.InitFields(n=None, z=None, theta=ctypes.c_void_p(0x10), ux=ctypes.c_void_p(0x10),
+                       uy=ctypes.c_void_p(0x10), given_z=0)
+    ctx = ctypes.c_void_p()
+    assert L.rlbm_init(ctypes.byref(ctx), ctypes.byref(p), ctypes.byref(fi)) == rl.RLBM_EINVAL
+
+
+def test_null_context_calls(rl):
+    L = rl.lib()
+    assert L.rlbm_step(None, 1) == rl.RLBM_EINVAL
+    assert L.rlbm_sync(None) == rl.RLBM_EINVAL
+    assert L.rlbm_state_index(None) == -1
+    L.rlbm_free(None)
