@@ -95,6 +95,40 @@ __device__ __forceinline__ void neighbours(const KArgs &a, int x, int y, int &xl
     if (yu >= a.ny) yu = (a.bc_yhi == RLBM_BC_PERIODIC) ? 0 : a.ny - 1;
 }
 
+// ---------------------------------------------------------------- buffer access
+// Populations are read and written with raw buffer instructions: one descriptor per
+// direction covers its 6 shell planes, the shell's plane offset is a scalar and
+// the cell's offset a 32-bit per-lane value, so no 64-bit per-lane address is formed.
+// The host keeps 6 * nx * ny * sizeof(element) below 2^32.
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void *base, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+template <typename S>
+__device__ __forceinline__ S bload(rsrc_t r, unsigned voff, unsigned soff);
+template <>
+__device__ __forceinline__ float bload<float>(rsrc_t r, unsigned voff, unsigned soff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+template <>
+__device__ __forceinline__ double bload<double>(rsrc_t r, unsigned voff, unsigned soff) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+
+template <typename S>
+__device__ __forceinline__ void bstore(S v, rsrc_t r, unsigned voff, unsigned soff);
+template <>
+__device__ __forceinline__ void bstore<float>(float v, rsrc_t r, unsigned voff, unsigned soff) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+}
+template <>
+__device__ __forceinline__ void bstore<double>(double v, rsrc_t r, unsigned voff, unsigned soff) {
+    typedef unsigned v2u __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u, v), r, voff, soff, 0);
+}
+
 // ---------------------------------------------------------------- streaming
 // Pull of all 72 populations of cell (x, y).  Axis directions shift by one cell;
 // the others interpolate bilinearly from (x, y), (xb, y), (x, yb), (xb, yb) with
@@ -104,25 +138,31 @@ __device__ __forceinline__ void neighbours(const KArgs &a, int x, int y, int &xl
 template <typename S, typename R>
 __device__ __forceinline__ void pull(const S *__restrict__ fin, long long plane, int nx, int x, int y, int xl,
                                      int xr, int yd, int yu, R (&f)[72]) {
-    const int oc = y * nx, od = yd * nx, ou = yu * nx;
+    constexpr unsigned E = sizeof(S);
+    const unsigned oc = (unsigned)(y * nx), od = (unsigned)(yd * nx), ou = (unsigned)(yu * nx);
+    const unsigned pb = (unsigned)plane * E;
     const R wA = (R)(S3H * 0.5);
     const R wB = (R)((1.0 - S3H) * 0.5);
 #pragma unroll
     for (int n = 0; n < 12; ++n) {
-        const int xb = cdir(n) > 0.1 ? xl : xr;     // source column x - sgn(v_x)
-        const int rb = sdir(n) > 0.1 ? od : ou;     // source row    y - sgn(v_y)
+        const rsrc_t r = make_rsrc(fin + (long long)(6 * n) * plane, 6u * pb);
+        const unsigned xb = cdir(n) > 0.1 ? xl : xr;     // source column x - sgn(v_x)
+        const unsigned rb = sdir(n) > 0.1 ? od : ou;     // source row    y - sgn(v_y)
+        const unsigned t_bb = (rb + xb) * E, t_bx = (rb + x) * E, t_cb = (oc + xb) * E, t_cx = (oc + x) * E;
 #pragma unroll
         for (int s = 0; s < 6; ++s) {
-            const S *__restrict__ p = fin + (long long)(6 * n + s) * plane;
+            const unsigned so = (unsigned)s * pb;
             R v;
-            if (n == 0) v = (R)p[oc + xl];
-            else if (n == 3) v = (R)p[od + x];
-            else if (n == 6) v = (R)p[oc + xr];
-            else if (n == 9) v = (R)p[ou + x];
+            if (n == 0) v = (R)bload<S>(r, (oc + xl) * E, so);
+            else if (n == 3) v = (R)bload<S>(r, (od + x) * E, so);
+            else if (n == 6) v = (R)bload<S>(r, (oc + xr) * E, so);
+            else if (n == 9) v = (R)bload<S>(r, (ou + x) * E, so);
             else if (n == 1 || n == 5 || n == 7 || n == 11)   // |v_x| = sqrt3/2, |v_y| = 1/2
-                v = wA * ((R)p[rb + xb] + (R)p[oc + xb]) + wB * ((R)p[rb + x] + (R)p[oc + x]);
+                v = wA * ((R)bload<S>(r, t_bb, so) + (R)bload<S>(r, t_cb, so)) +
+                    wB * ((R)bload<S>(r, t_bx, so) + (R)bload<S>(r, t_cx, so));
             else                                              // |v_x| = 1/2, |v_y| = sqrt3/2
-                v = wA * ((R)p[rb + xb] + (R)p[rb + x]) + wB * ((R)p[oc + xb] + (R)p[oc + x]);
+                v = wA * ((R)bload<S>(r, t_bb, so) + (R)bload<S>(r, t_bx, so)) +
+                    wB * ((R)bload<S>(r, t_cb, so) + (R)bload<S>(r, t_cx, so));
             f[6 * n + s] = v;
         }
     }
@@ -298,13 +338,18 @@ __device__ __forceinline__ double invert_h(double r, double mu, unsigned &flags)
         const double q = g[2] / g[3];
         const double h = g[2] * q * q;
         const double F = h - r;
+        const double dmu = F / (h * (3.0 * g[1] / g[2] - 2.0 * q));   // dh/dmu = h (3 g1/g2 - 2 g2/g3)
+        const double tol = 1e-12 * fmax(1.0, fabs(mu));
+        if (F == 0.0 || fabs(dmu) <= tol) {   // quadratic convergence: the residual error is O(dmu^2)
+            mu -= (F == 0.0) ? 0.0 : dmu;
+            conv = true;
+            break;
+        }
         if (F > 0) hi = mu; else lo = mu;
-        const double dh = h * (3.0 * g[1] / g[2] - 2.0 * q);
-        double mn = mu - F / dh;
-        if (!(mn > lo && mn < hi)) mn = 0.5 * (lo + hi);
-        const double step = fabs(mn - mu);
+        double mn = mu - dmu;
+        if (!(mn > lo && mn < hi)) mn = 0.5 * (lo + hi);   // safeguard: keep inside the bracket
         mu = mn;
-        if (step <= 1e-12 * fmax(1.0, fabs(mu)) || hi - lo <= 4e-16 * fmax(1.0, fabs(mu))) {
+        if (hi - lo <= 4e-16 * fmax(1.0, fabs(mu))) {
             conv = true;
             break;
         }
@@ -318,23 +363,36 @@ template <int ST>
 __device__ __forceinline__ double invert_g2(double target, unsigned &flags) {
     double lo = -40.0, hi = (ST == RLBM_BE) ? LOG_ZC_BE : FD_MU_MIN + (FD_NC - 0.5) * FD_DMU;
     double mu = (ST == RLBM_BE) ? -0.6931471805599453 : 0.0;
+    if (ST == RLBM_BE) {
+        double g[7];
+        gvals<ST, 1, 2>(LOG_ZC_BE, g, flags);
+        if (!(target < g[2])) {   // density above the condensation bound at this theta
+            flags |= RLBM_FLAG_CONDENSED;
+            return LOG_ZC_BE;
+        }
+    }
     bool conv = false;
     for (int it = 0; it < 80; ++it) {
         double g[7];
         gvals<ST, 1, 2>(mu, g, flags);
         const double F = g[2] - target;
+        const double dmu = F / g[1];            // d g_2 / d mu = g_1
+        const double tol = 1e-12 * fmax(1.0, fabs(mu));
+        if (F == 0.0 || fabs(dmu) <= tol) {
+            mu -= (F == 0.0) ? 0.0 : dmu;
+            conv = true;
+            break;
+        }
         if (F > 0) hi = mu; else lo = mu;
-        double mn = mu - F / g[1];
+        double mn = mu - dmu;
         if (!(mn > lo && mn < hi)) mn = 0.5 * (lo + hi);
-        const double step = fabs(mn - mu);
         mu = mn;
-        if (step <= 1e-12 * fmax(1.0, fabs(mu)) || hi - lo <= 4e-16 * fmax(1.0, fabs(mu))) {
+        if (hi - lo <= 4e-16 * fmax(1.0, fabs(mu))) {
             conv = true;
             break;
         }
     }
     if (!conv) flags |= RLBM_FLAG_NOCONV;
-    if (ST == RLBM_BE && mu >= LOG_ZC_BE) flags |= RLBM_FLAG_CONDENSED;
     return mu;
 }
 
@@ -489,8 +547,15 @@ __device__ __forceinline__ void equilibrium_relax(const Macro &M, double tau, R 
 
 template <typename S, typename R>
 __device__ __forceinline__ void store(S *__restrict__ fout, long long plane, int off, const R (&f)[72]) {
+    constexpr unsigned E = sizeof(S);
+    const unsigned pb = (unsigned)plane * E;
+    const unsigned vo = (unsigned)off * E;
 #pragma unroll
-    for (int q = 0; q < 72; ++q) fout[(long long)q * plane + off] = (S)f[q];
+    for (int n = 0; n < 12; ++n) {
+        const rsrc_t r = make_rsrc(fout + (long long)(6 * n) * plane, 6u * pb);
+#pragma unroll
+        for (int s = 0; s < 6; ++s) bstore<S>((S)f[6 * n + s], r, vo, (unsigned)s * pb);
+    }
 }
 
 __device__ __forceinline__ void report(unsigned *status, unsigned flags) {
@@ -612,7 +677,10 @@ namespace {
 int validate(const rlbm_params *p) {
     if (!p) return RLBM_EINVAL;
     if (p->nx < 2 || p->ny < 2) return RLBM_EINVAL;
-    if ((long long)p->nx * p->ny > (1LL << 31) - 1) return RLBM_EINVAL;
+    {
+        const long long elem = p->precision == RLBM_FP64 ? 8 : 4;
+        if (6LL * p->nx * p->ny * elem > 0xFFFFFFFFLL) return RLBM_EINVAL;   // one buffer descriptor per direction
+    }
     if (p->stats < RLBM_MJ || p->stats > RLBM_BE) return RLBM_EINVAL;
     if (p->order != 5) return (p->order >= 2 && p->order <= 4) ? RLBM_ENOTIMPL : RLBM_EINVAL;
     if (p->precision != RLBM_FP64 && p->precision != RLBM_FP32) return RLBM_EINVAL;

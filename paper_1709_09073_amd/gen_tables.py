@@ -200,20 +200,21 @@ def emit(path):
         w_all.append([l * 2 * mp.pi / 12 for l in lam])
         E_all.append(separable_projector(st, nodes, lam))
     lines.append("// radial nodes p_s and per-vector weights w_s, [stats][shell]; stats: 0 MJ, 1 FD, 2 BE")
-    lines.append("__constant__ double P_SHELL[3][6] = {%s};" % ", ".join(
+    lines.append("constexpr double P_SHELL[3][6] = {%s};" % ", ".join(
         "{" + ", ".join(_fmt(x) for x in p) + "}" for p in p_all))
-    lines.append("__constant__ double W_SHELL[3][6] = {%s};" % ", ".join(
+    lines.append("constexpr double W_SHELL[3][6] = {%s};" % ", ".join(
         "{" + ", ".join(_fmt(x) for x in w) + "}" for w in w_all))
     pairs = [(j, k) for j in range(6) for k in range(j, 6)]
     lines.append("// separable projector E[stats][pair][shell], pair = (j, k) j-major, k = j..5")
+    lines.append("// (constexpr tables are only indexed with compile-time indices: values fold into instructions)")
     body = []
     for E in E_all:
         body.append("{" + ", ".join("{" + ", ".join(_fmt(E[(j, k, s)]) for s in range(6)) + "}" for (j, k) in pairs) + "}")
-    lines.append("__constant__ double EMAT[3][21][6] = {%s};" % ", ".join(body))
+    lines.append("constexpr double EMAT[3][21][6] = {%s};" % ", ".join(body))
     P = pkj_polynomials()
     lines.append("// P_kj(x) = c0 + c1 x + c2 x^2 including the factor 2 pi, per pair (j, k)")
     with mp.workdps(DPS):
-        lines.append("__constant__ double PKJ[21][3] = {%s};" % ", ".join(
+        lines.append("constexpr double PKJ[21][3] = {%s};" % ", ".join(
             "{" + ", ".join(_fmt(2 * mp.pi * mp.mpf(c.numerator) / c.denominator) for c in P[(j, k)]) + "}"
             for (j, k) in pairs))
     # g tables
@@ -231,9 +232,9 @@ def emit(path):
         zs = [(mp.zeta(m) if m != 1 else mp.mpf(0)) for m in range(6, 6 - BE_NZ - 6, -1)]
         lines.append("// zeta(m) for m = 6 .. %d (m = 1 stored as 0), series of Li about mu = 0" % (6 - BE_NZ - 5))
         lines.append("__constant__ double BE_ZETA[%d] = {%s};" % (len(zs), ", ".join(_fmt(x) for x in zs)))
-        lines.append("__constant__ double HARMONIC[6] = {%s};" % ", ".join(
+        lines.append("constexpr double HARMONIC[6] = {%s};" % ", ".join(
             _fmt(mp.fsum(mp.mpf(1) / i for i in range(1, m + 1))) for m in range(6)))
-        lines.append("__constant__ double INV_FACT[%d] = {%s};" % (BE_NZ + 1, ", ".join(
+        lines.append("constexpr double INV_FACT[%d] = {%s};" % (BE_NZ + 1, ", ".join(
             _fmt(1 / mp.factorial(i)) for i in range(BE_NZ + 1))))
     lines += ["", "}  // namespace rlbm_tab", ""]
     with open(path, "w") as fh:

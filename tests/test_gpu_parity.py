@@ -1,11 +1,18 @@
 """Parity of the HIP path (through the C ABI) with the FP64 oracle.
 
-FP64 storage: fields n, eps, theta, z, u to 1e-12 relative (max norm); the heat
-flux, a cancellation moment, to 1e-11 of its max norm; populations per radial
-shell relative to that shell's max (the outer shells carry the rounding of the
-ill-conditioned radial projection: see the oracle's brute-force comparison).
-FP32 storage: the tolerances derived in the design doc (populations stored with
-2^-24 relative rounding; a few units of it per step).
+Bars (FP64 populations).  Both sides round independently; the oracle against its
+brute-force checker drifts by about 3e-15 relative per step in eps, so after K steps
+the bars scale with g(K) = max(1, K/100):
+  * n, eps: relative max-norm error <= 1e-12 g(K); theta = eps/2n (MJ) and
+    z = 2 n^3/(pi eps^2) (MJ) propagate them: theta <= 2e-12 g(K), z <= 5e-12 g(K);
+  * u_x, u_y: error <= 1e-12 g(K) max(|u|_max, 0.01)  (u is measured against c = 1;
+    the floor keeps near-rest flows from dividing rounding by a tiny maximum);
+  * q_x, q_y (cancellation moments n U - N): <= 1e-11 g(K) max(|q|_max, 1e-3 eps_max);
+  * populations per radial shell, relative to that shell's maximum:
+    (2e-12, 2e-12, 2e-12, 5e-12, 2e-11, 2e-10) g(K); the outer shells carry the rounding
+    of the ill-conditioned radial projection.
+One step from the same non-equilibrium state must agree to 1e-13 in the fields.
+FP32 populations: bars derived from 2^-24 storage rounding.
 """
 import numpy as np
 import pytest
@@ -16,9 +23,14 @@ from oracle import lattice as L
 
 pytestmark = pytest.mark.gpu
 
-SHELL_TOL_FP64 = (2e-13, 2e-13, 2e-13, 1e-12, 5e-12, 5e-11)
-FIELD_TOL_FP64 = dict(n=1e-12, eps=1e-12, theta=1e-12, z=1e-12, ux=1e-12, uy=1e-12, qx=1e-11, qy=1e-11)
+SHELL_TOL_FP64 = (2e-12, 2e-12, 2e-12, 5e-12, 2e-11, 2e-10)
+FIELD_TOL_FP64 = dict(n=1e-12, eps=1e-12, theta=2e-12, z=5e-12, ux=1e-12, uy=1e-12, qx=1e-11, qy=1e-11)
 FIELD_TOL_FP32 = dict(n=2e-6, eps=2e-6, theta=2e-6, z=5e-6, ux=2e-5, uy=2e-5, qx=2e-3, qy=2e-3)
+FLOOR = dict(ux=("abs", 0.01), uy=("abs", 0.01), qx=("eps", 1e-3), qy=("eps", 1e-3))
+
+
+def growth(k):
+    return max(1.0, k / 100.0)
 
 
 @pytest.fixture(scope="module")
@@ -42,18 +54,27 @@ def _oracle_init(op, fields):
     return L.init_state(op, f["theta"], f["ux"], f["uy"], n=f.get("n"), z=f.get("z"))
 
 
-def _compare_fields(a, b, tol, ctx):
+def _scale(k, b):
+    ref = np.abs(b[k]).max()
+    if k in FLOOR:
+        kind, fl = FLOOR[k]
+        ref = max(ref, fl if kind == "abs" else fl * np.abs(b["eps"]).max())
+    return max(ref, 1e-300)
+
+
+def _compare_fields(a, b, tol, ctx, g=1.0):
     for k, t in tol.items():
-        ref = b[k]
-        err = np.abs(a[k] - ref).max() / max(np.abs(ref).max(), 1e-300)
-        assert err <= t, f"{ctx}: field {k} rel err {err:.3e} > {t:.1e}"
+        err = np.abs(a[k] - b[k]).max() / _scale(k, b)
+        print(f"  {ctx}: {k} err {err:.2e} (bar {t * g:.1e})")
+        assert err <= t * g, f"{ctx}: field {k} rel err {err:.3e} > {t * g:.1e}"
 
 
-def _compare_pops(a, b, tols, ctx):
+def _compare_pops(a, b, tols, ctx, g=1.0):
     for k, t in enumerate(tols):
         sl = slice(k, 72, 6)
         err = np.abs(a[sl] - b[sl]).max() / np.abs(b[sl]).max()
-        assert err <= t, f"{ctx}: shell {k} rel err {err:.3e} > {t:.1e}"
+        print(f"  {ctx}: shell {k} err {err:.2e} (bar {t * g:.1e})")
+        assert err <= t * g, f"{ctx}: shell {k} rel err {err:.3e} > {t * g:.1e}"
 
 
 def _run(rl, stats, precision, params, fields, nsteps):
@@ -88,8 +109,8 @@ def test_fp64_parity(rl, stats, nx, ny, nsteps, bc, tau_mode):
     params = dict(nx=nx, ny=ny, bc=bc, tau_mode=tau_mode, tau=0.85, tau_a=0.6, tau_b=0.6)
     pops, flds, fo, flo = _run(rl, stats, "fp64", params, fields, nsteps)
     ctx = f"{stats} fp64 {nx}x{ny} {bc[0]}"
-    _compare_pops(pops, fo, SHELL_TOL_FP64, ctx)
-    _compare_fields(flds, flo, FIELD_TOL_FP64, ctx)
+    _compare_pops(pops, fo, SHELL_TOL_FP64, ctx, growth(nsteps))
+    _compare_fields(flds, flo, FIELD_TOL_FP64, ctx, growth(nsteps))
 
 
 @pytest.mark.parametrize("stats", ["MJ", "FD", "BE"])
@@ -106,7 +127,7 @@ def test_fp64_walls(rl, stats):
     params, fields = workloads.fourier(nx=40, ny=4, dT=0.05, tau=0.9)
     pops, flds, fo, flo = _run(rl, stats, "fp64", params, fields, 4)
     _compare_pops(pops, fo, SHELL_TOL_FP64, f"{stats} walls")
-    _compare_fields(flds, flo, dict(FIELD_TOL_FP64, qx=1e-10, qy=1e-9), f"{stats} walls")
+    _compare_fields(flds, flo, FIELD_TOL_FP64, f"{stats} walls")
 
 
 @pytest.mark.parametrize("stats,nsteps", [("MJ", 8), ("FD", 3), ("BE", 3)])
@@ -117,11 +138,35 @@ def test_fp32_parity(rl, stats, nsteps):
     _compare_fields(flds, flo, FIELD_TOL_FP32, f"{stats} fp32")
 
 
+@pytest.mark.parametrize("stats", ["MJ", "FD", "BE"])
+def test_fp64_single_step_from_oracle_state(rl, stats):
+    """One GPU step from a non-equilibrium state produced by the oracle (copied into
+    the caller-owned population buffer) against the oracle's next step."""
+    nx, ny = 69, 11
+    fields = workloads.smooth_random(nx, ny, seed=21, stats=stats, amp_u=0.2)
+    op = _oracle_params(dict(nx=nx, ny=ny, tau=0.7), stats)
+    f = _oracle_init(op, fields)
+    for _ in range(15):
+        f, _ = L.step(f, op)
+    print(f"[parity] {stats} single step from oracle state {nx}x{ny}", flush=True)
+    sim = rl.Sim(dict(nx=nx, ny=ny, stats=stats, precision="fp64", tau=0.7), {k: v.cuda() for k, v in fields.items()})
+    sim.state().copy_(torch.from_numpy(f))
+    sim.step(1)
+    pops = sim.state().cpu().numpy()
+    flds = {k: v.cpu().numpy() for k, v in sim.fields().items()}
+    sim.close()
+    f1, _ = L.step(f, op)
+    ref = L.fields(f1, op)
+    _compare_pops(pops, f1, [t / 10 for t in SHELL_TOL_FP64], f"{stats} one step")
+    _compare_fields(flds, ref, {k: v / 10 for k, v in FIELD_TOL_FP64.items()}, f"{stats} one step")
+
+
 def test_riemann_fp64_full_config(rl):
     """Shock tube MJ, 1024 x 4, FP64, tau = 0.9, 500 steps: the small configuration."""
     params, fields = workloads.riemann(nx=1024, ny=4, tau=0.9)
     pops, flds, fo, flo = _run(rl, "MJ", "fp64", params, fields, 500)
-    _compare_fields(flds, flo, dict(FIELD_TOL_FP64, qx=1e-10, qy=1e-10), "riemann")
+    _compare_pops(pops, fo, SHELL_TOL_FP64, "riemann", growth(500))
+    _compare_fields(flds, flo, FIELD_TOL_FP64, "riemann", growth(500))
 
 
 def test_minimal_grid(rl):
