@@ -46,6 +46,29 @@ def build_workload(name, device):
     return params, fields
 
 
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in ("paper_1709_09073_amd/csrc/rlbm.hip", "paper_1709_09073_amd/csrc/rlbm_tables.h"):
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(workload, precision):
+    """HBM bytes per launch from the committed rocprofv3 counter runs, if they were taken
+    on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh).get(f"{workload}/{precision}")
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("source_sha256") != kernel_source_hash():
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
 def cpu_baseline(name, budget_s=15.0):
     """Time the FP64 oracle (as it stands) on a bounded sample: a 64 x 64 window of
     the same workload's initial fields, as many steps as fit the budget."""
@@ -141,7 +164,8 @@ def main():
                    "order": 5, "lattice": "d2v72", "populations": args.precision, "inversion_guess": "fixed",
                    "status_bits": status},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": recorded_traffic(args.workload, args.precision),
                      "algorithmic_bytes_per_launch": bytes_per_launch, "kernel": "k_step"},
     }
     if not args.no_cpu_baseline:
