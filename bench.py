@@ -24,6 +24,7 @@ WORKLOADS = {
     "fd_hotspot_2048": "Fermi-Dirac hot spot 2048x2048, Gaussian theta bump (amp 0.3, sigma 64) on theta = 1, "
                        "seeded fugacity in [0.5, 2], tau = 2/theta + 0.2546, open boundaries",
     "taylor_green_512": "Taylor-Green vortex 512x512 periodic, MJ, u0 = 0.05, theta = n = 1, tau = 0.8",
+    "taylor_green_2048": "Taylor-Green vortex 2048x2048 periodic, MJ, u0 = 0.05, theta = n = 1, tau = 0.8",
     "be_hotspot_8192": "Bose-Einstein 8192x8192, 16 seeded Gaussian theta/fugacity bumps, tau = 2/theta + 0.2546, open",
     "riemann_1024x4": "Riemann shock tube MJ 1024x4, n 1.0/0.139, theta = 1, tau = 0.9, x open, y periodic",
 }
@@ -35,6 +36,9 @@ def build_workload(name, device):
         params, fields = workloads.hotspot_fd(L=2048, device=device)
     elif name == "taylor_green_512":
         params, fields = workloads.taylor_green(L=512, tau=0.8, device=device)
+        params["stats"] = "MJ"
+    elif name == "taylor_green_2048":
+        params, fields = workloads.taylor_green(L=2048, tau=0.8, device=device)
         params["stats"] = "MJ"
     elif name == "be_hotspot_8192":
         params, fields = workloads.hotspot_be(L=8192, device=device)
@@ -100,6 +104,33 @@ def cpu_baseline(name, budget_s=15.0):
                        f"in {dt:.1f} s")
 
 
+def train_guess_net(name, device):
+    """Train the inversion-guess network on (ln r, ln z) pairs from a 512^2 run of the
+    same workload family (100 steps), with the library's training kernels."""
+    import numpy as np
+    import torch
+    import workloads
+    from paper_1709_09073_amd import rlbm
+    if name.startswith("fd_hotspot"):
+        params, fields = workloads.hotspot_fd(L=512, seed=11, sigma=16.0, device=device)
+    elif name.startswith("be_hotspot"):
+        params, fields = workloads.hotspot_be(L=512, seed=11, device=device)
+    else:
+        return None, None
+    sim = rlbm.Sim(dict(params, precision="fp32"), fields)
+    sim.step(100)
+    x, t = sim.inversion_samples()
+    sim.close()
+    net = rlbm.GuessNet()
+    noise = torch.from_numpy(np.random.default_rng(0).standard_normal(rlbm.MLP_HIDDEN + 1).astype(np.float32)).to(device)
+    net.init(x, t, noise)
+    losses = net.train(x, t, iters=3000, lr=3e-3)
+    torch.cuda.synchronize()
+    err = (net.predict(x) - t.reshape(-1)).abs().max().item()
+    return net, dict(samples=int(x.numel()), iters=3000, loss_first=float(losses[0]), loss_last=float(losses[-1]),
+                     max_abs_err_ln_z=err)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -108,6 +139,9 @@ def main():
     ap.add_argument("--workload", default="fd_hotspot_2048", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tile", default="auto", help="workgroup tile TXxTY (e.g. 64x4) or auto")
+    ap.add_argument("--guess", default="fixed", choices=["fixed", "mlp"],
+                    help="FD/BE inversion start: fixed, or the network trained on a smaller run first")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -120,8 +154,16 @@ def main():
     dev = "cuda"
     params, fields = build_workload(args.workload, dev)
     params["precision"] = args.precision
+    if args.tile != "auto":
+        params["tile"] = tuple(int(v) for v in args.tile.split("x"))
     print(f"[bench] workload={args.workload} precision={args.precision} grid={params['nx']}x{params['ny']} "
           f"warmup={args.warmup} steps={args.steps}", file=sys.stderr, flush=True)
+    net, net_info = (None, None)
+    if args.guess == "mlp":
+        net, net_info = train_guess_net(args.workload, dev)
+        if net is not None:
+            params["guess"] = "mlp"
+            params["mlp"] = net.w
     sim = rlbm.Sim(params, fields)
     del fields
     sim.step(args.warmup)
@@ -161,7 +203,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "description": WORKLOADS[args.workload],
                    "grid": [params["nx"], params["ny"]], "statistic": params.get("stats", "MJ"),
-                   "order": 5, "lattice": "d2v72", "populations": args.precision, "inversion_guess": "fixed",
+                   "order": 5, "lattice": "d2v72", "populations": args.precision, "inversion_guess": args.guess, "guess_net": net_info, "tile": args.tile,
                    "status_bits": status},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),

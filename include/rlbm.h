@@ -89,6 +89,9 @@ typedef struct rlbm_params {
     const float *mlp;        /* device pointer to the MLP weights (RLBM_GUESS_MLP), else NULL */
     void *f_a, *f_b;         /* device population buffers (ping-pong), 72*nx*ny elements each */
     void *stream;            /* hipStream_t, NULL = default stream */
+    int32_t tile_x, tile_y;  /* cells per workgroup tile, tile_x * tile_y = 256 with tile_x a power
+                                of two >= 16; 0, 0 = automatic (32 x 8; 64 x 4 or 128 x 2 for ny < 8, 4) */
+    int32_t collect_stats;   /* 1: count Newton iterations of the FD/BE inversion (rlbm_inversion_stats) */
 } rlbm_params;
 
 typedef struct rlbm_init_fields {
@@ -130,6 +133,53 @@ int rlbm_sync(rlbm_ctx *ctx);
 
 /* Wait for the stream and return the status-word bits without clearing them. */
 uint32_t rlbm_status(rlbm_ctx *ctx);
+
+/* Newton iterations and solves of the FD/BE (n, eps) -> (theta, z) inversion summed
+ * over all step launches since rlbm_init (collect_stats = 1; otherwise zeros).
+ * Synchronises the stream.  Errors: RLBM_EINVAL, RLBM_EHIP. */
+int rlbm_inversion_stats(rlbm_ctx *ctx, uint64_t *iterations, uint64_t *solves);
+
+/* Training pairs from the current state, one per cell (FP32 device arrays of
+ * nx*ny): x = ln r with r = 2 n^3 / (pi eps^2), t = ln z, from the same moments,
+ * Landau frame and inversion as rlbm_moments.  Synchronises the stream. */
+int rlbm_inversion_samples(rlbm_ctx *ctx, float *x, float *t);
+
+/* ---- the inversion-guess network (project extension, not in the paper) -------
+ * One hidden layer of RLBM_MLP_HIDDEN ReLU units maps L = ln r to mu = ln z; it
+ * supplies the starting point of the safeguarded Newton solve, which still
+ * decides the result.  Weight buffer: RLBM_MLP_FLOATS floats in device memory,
+ * layout [a, b, m, s, W1[H], b1[H], W2[H], b2] with x = (L - a) b and
+ * mu = m + s (b2 + sum_h W2_h max(W1_h x + b1_h, 0)).  The loss is the mean over
+ * samples of (y - (t - m)/s)^2.  All arrays are caller-owned device memory;
+ * calls are asynchronous on `stream` (hipStream_t, NULL = default). */
+#define RLBM_MLP_HIDDEN 32
+#define RLBM_MLP_FLOATS (4 + 3 * RLBM_MLP_HIDDEN + 1)
+#define RLBM_MLP_NTRAIN (3 * RLBM_MLP_HIDDEN + 1)
+
+/* Bytes of device workspace the training calls need for n samples. */
+uint64_t rlbm_mlp_workspace_bytes(int64_t n);
+
+/* Initialise w from the data (n >= 2): a, b map [min x, max x] to [-1, 1]; m, s are
+ * the mean and standard deviation of t; hidden unit h gets W1 = 1 and its kink at
+ * x = -1 + 2(h + 1/2)/H; W2 and b2 are noise[0..H] * 0.1 (noise: H + 1 caller-drawn
+ * standard normals, device floats).  Errors: RLBM_EINVAL, RLBM_EHIP. */
+int rlbm_mlp_init(float *w, const float *x, const float *t, int64_t n, const float *noise, void *workspace,
+                  void *stream);
+
+/* Full-batch loss and its gradient with respect to the RLBM_MLP_NTRAIN trainable
+ * parameters (order W1, b1, W2, b2), summed in a fixed order (deterministic).
+ * grad and loss are device floats. */
+int rlbm_mlp_loss_grad(const float *w, const float *x, const float *t, int64_t n, float *grad, float *loss,
+                       void *workspace, void *stream);
+
+/* iters steps of Adam (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr) on the
+ * full batch, updating the trainable part of w in place.  loss_out (device, may be
+ * NULL) receives the loss before each step (iters floats). */
+int rlbm_mlp_train(float *w, const float *x, const float *t, int64_t n, int32_t iters, float lr,
+                   float *loss_out, void *workspace, void *stream);
+
+/* y[i] = network(x[i]) for n inputs (device floats). */
+int rlbm_mlp_predict(const float *w, const float *x, float *y, int64_t n, void *stream);
 
 /* Release the context (not the caller's buffers).  NULL is a no-op. */
 void rlbm_free(rlbm_ctx *ctx);

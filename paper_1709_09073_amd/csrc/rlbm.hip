@@ -25,7 +25,12 @@
 #include <new>
 
 #include "rlbm.h"
+#include "rlbm_mlp.h"
 #include "rlbm_tables.h"
+
+#ifndef RLBM_STEP_WAVES_PER_SIMD
+#define RLBM_STEP_WAVES_PER_SIMD 3   // occupancy target of the step kernel (register budget 512/3)
+#endif
 
 namespace {
 
@@ -59,6 +64,8 @@ struct KArgs {
     int guess;
     const float *mlp;
     unsigned *status;
+    unsigned long long *stats;   // [0] Newton iterations, [1] solves (NULL: not collected)
+    float *o_mlx, *o_mlt;        // inversion training pairs (moments kernel)
     // init inputs
     const double *i_n, *i_z, *i_theta, *i_ux, *i_uy;
     int given_z;
@@ -320,7 +327,7 @@ __device__ __forceinline__ void gvals(double mu, double (&g)[7], unsigned &flags
 
 // Solve h(mu) = g_2^3/g_3^2 = r for mu = ln z (FD, BE), safeguarded Newton.
 template <int ST>
-__device__ __forceinline__ double invert_h(double r, double mu, unsigned &flags) {
+__device__ __forceinline__ double invert_h(double r, double mu, unsigned &flags, int &iters) {
     double lo = -40.0, hi = (ST == RLBM_BE) ? LOG_ZC_BE : FD_MU_MIN + (FD_NC - 0.5) * FD_DMU;
     if (ST == RLBM_BE) {
         double g[7];
@@ -332,7 +339,9 @@ __device__ __forceinline__ double invert_h(double r, double mu, unsigned &flags)
     }
     if (!(mu > lo && mu < hi)) mu = 0.5 * (lo + hi);
     bool conv = false;
+    iters = 0;
     for (int it = 0; it < 80; ++it) {
+        ++iters;
         double g[7];
         gvals<ST, 1, 3>(mu, g, flags);
         const double q = g[2] / g[3];
@@ -403,7 +412,8 @@ struct Macro {
 };
 
 template <int ST>
-__device__ __forceinline__ void state_from_moments(const Mom &m, Macro &M, unsigned &flags, double mu_guess) {
+__device__ __forceinline__ void state_from_moments(const Mom &m, Macro &M, unsigned &flags, const KArgs &a,
+                                                   int &iters, double *L_out = nullptr) {
     landau(m, M.ux, M.uy, M.eps, flags);
     const double u2 = M.ux * M.ux + M.uy * M.uy;
     if (!(u2 < 1.0)) {
@@ -418,13 +428,18 @@ __device__ __forceinline__ void state_from_moments(const Mom &m, Macro &M, unsig
         M.eps = M.eps > 0.0 ? M.eps : 1.0;
     }
     const double r = 2.0 * M.n * M.n * M.n / (PI_D * M.eps * M.eps);
+    if (L_out) *L_out = log(r);
+    iters = 0;
     if constexpr (ST == RLBM_MJ) {
         M.theta = M.eps / (2.0 * M.n);
         M.z = r;
 #pragma unroll
         for (int k = 1; k <= 6; ++k) M.g[k] = r;
     } else {
-        const double mu = invert_h<ST>(r, mu_guess, flags);
+        // starting point of the Newton solve: the trained network, or the fixed guess
+        double mu0 = (ST == RLBM_BE) ? -0.6931471805599453 : 0.0;
+        if (a.guess == RLBM_GUESS_MLP) mu0 = (double)rlbm_mlp::eval(a.mlp, logf((float)r));
+        const double mu = invert_h<ST>(r, mu0, flags, iters);
         gvals<ST, 1, 6>(mu, M.g, flags);
         M.z = exp(mu);
         M.theta = 0.5 * (M.g[2] / M.g[3]) * (M.eps / M.n);
@@ -564,7 +579,7 @@ __device__ __forceinline__ void report(unsigned *status, unsigned flags) {
 
 // ---------------------------------------------------------------- kernels
 template <int ST, typename S, typename R>
-__global__ __launch_bounds__(256) void k_step(KArgs a) {
+__global__ __launch_bounds__(256, RLBM_STEP_WAVES_PER_SIMD) void k_step(KArgs a) {
     int x, y;
     if (!cell_of(a, x, y)) return;
     unsigned flags = 0;
@@ -577,8 +592,18 @@ __global__ __launch_bounds__(256) void k_step(KArgs a) {
     pull<S, R>((const S *)a.fin, a.plane, a.nx, xe, y, xl, xr, yd, yu, f);
     const Mom m = moments<ST, R>(f);
     Macro M;
-    const double mu0 = (ST == RLBM_BE) ? -0.6931471805599453 : 0.0;
-    state_from_moments<ST>(m, M, flags, mu0);
+    int iters;
+    state_from_moments<ST>(m, M, flags, a, iters);
+    if (ST != RLBM_MJ && a.stats) {
+        // one atomic per wavefront: sum the lanes' iteration counts first
+        unsigned long long it = (unsigned long long)iters;
+        if (__activemask() == ~0ull) {
+            for (int off = 32; off > 0; off >>= 1) it += __shfl_down(it, off, 64);
+            if ((threadIdx.x & 63) == 0) atomicAdd(&a.stats[0], it);
+        } else {
+            atomicAdd(&a.stats[0], it);   // partial wavefront at the grid edge
+        }
+    }
     if (wall_lo || wall_hi) {
         // zeroth-order extrapolation of n and u, fixed wall temperature
         const double n = M.n;
@@ -603,9 +628,12 @@ __global__ __launch_bounds__(256) void k_moments(KArgs a) {
     pull<S, R>((const S *)a.fin, a.plane, a.nx, x, y, xl, xr, yd, yu, f);
     const Mom m = moments<ST, R>(f);
     Macro M;
-    const double mu0 = (ST == RLBM_BE) ? -0.6931471805599453 : 0.0;
-    state_from_moments<ST>(m, M, flags, mu0);
+    int iters;
+    double L;
+    state_from_moments<ST>(m, M, flags, a, iters, &L);
     const int off = y * a.nx + x;
+    if (a.o_mlx) a.o_mlx[off] = (float)L;
+    if (a.o_mlt) a.o_mlt[off] = (float)log(M.z);
     const double hE = 3.0 * M.theta * M.g[3] / M.g[2];
     if (a.o_n) a.o_n[off] = M.n;
     if (a.o_eps) a.o_eps[off] = M.eps;
@@ -667,6 +695,8 @@ struct rlbm_ctx {
     KArgs base;
     hipStream_t stream;
     unsigned *status;     // device status word
+    unsigned long long *stats;   // device inversion counters (collect_stats)
+    int64_t stat_steps;   // steps launched with counting on
     int cur;              // 0: f_a holds the state, 1: f_b
     int64_t steps;
     dim3 grid, block;
@@ -699,15 +729,24 @@ int validate(const rlbm_params *p) {
     if ((p->bc[0] == RLBM_BC_WALL_T || p->bc[1] == RLBM_BC_WALL_T) && p->nx < 4) return RLBM_EINVAL;
     for (int i = 0; i < 2; ++i)
         if (p->bc[i] == RLBM_BC_WALL_T && !(p->theta_wall[i] > 0.0)) return RLBM_EINVAL;
-    if (p->guess != RLBM_GUESS_FIXED) return RLBM_ENOTIMPL;
+    if (p->guess != RLBM_GUESS_FIXED && p->guess != RLBM_GUESS_MLP) return RLBM_EINVAL;
+    if (p->guess == RLBM_GUESS_MLP && !p->mlp) return RLBM_EINVAL;
+    if (p->tile_x != 0 || p->tile_y != 0) {
+        const int tx = p->tile_x, ty = p->tile_y;
+        if (tx < 16 || ty < 1 || tx * ty != 256 || (tx & (tx - 1))) return RLBM_EINVAL;
+    }
     if (!p->f_a || !p->f_b || p->f_a == p->f_b) return RLBM_EINVAL;
     return RLBM_OK;
 }
 
-void tile_shape(int nx, int ny, int &tx, int &ty) {
-    ty = ny >= 4 ? 4 : (ny >= 2 ? 2 : 1);
+void tile_shape(const rlbm_params *p, int &tx, int &ty) {
+    if (p->tile_x > 0) {
+        tx = p->tile_x;
+        ty = p->tile_y;
+        return;
+    }
+    ty = p->ny >= 8 ? 8 : (p->ny >= 4 ? 4 : 2);   // 32 x 8 measured fastest on 2048^2 grids
     tx = 256 / ty;
-    (void)nx;
 }
 
 }  // namespace
@@ -728,17 +767,25 @@ int rlbm_init(rlbm_ctx **out, const rlbm_params *p, const rlbm_init_fields *init
         delete c;
         return RLBM_EHIP;
     }
-    if (hipMemsetAsync(c->status, 0, sizeof(unsigned), c->stream) != hipSuccess) {
-        hipFree(c->status);
+    if (hipMalloc(&c->stats, 2 * sizeof(unsigned long long)) != hipSuccess) {
+        (void)hipFree(c->status);
         delete c;
         return RLBM_EHIP;
     }
+    if (hipMemsetAsync(c->status, 0, sizeof(unsigned), c->stream) != hipSuccess ||
+        hipMemsetAsync(c->stats, 0, 2 * sizeof(unsigned long long), c->stream) != hipSuccess) {
+        (void)hipFree(c->status);
+        (void)hipFree(c->stats);
+        delete c;
+        return RLBM_EHIP;
+    }
+    c->stat_steps = 0;
     KArgs &a = c->base;
     a = KArgs{};
     a.nx = p->nx;
     a.ny = p->ny;
     a.plane = (long long)p->nx * p->ny;
-    tile_shape(p->nx, p->ny, a.tx, a.ty);
+    tile_shape(p, a.tx, a.ty);
     a.ntx = (p->nx + a.tx - 1) / a.tx;
     a.ntiles = a.ntx * ((p->ny + a.ty - 1) / a.ty);
     a.per_xcd = (a.ntiles + 7) / 8;
@@ -755,6 +802,7 @@ int rlbm_init(rlbm_ctx **out, const rlbm_params *p, const rlbm_init_fields *init
     a.guess = p->guess;
     a.mlp = p->mlp;
     a.status = c->status;
+    a.stats = p->collect_stats ? c->stats : nullptr;
     c->grid = dim3(8 * a.per_xcd);
     c->block = dim3(256);
     c->cur = 0;
@@ -769,7 +817,8 @@ int rlbm_init(rlbm_ctx **out, const rlbm_params *p, const rlbm_init_fields *init
     ia.given_z = init->given_z;
     hipLaunchKernelGGL(pick(2, p->stats, p->precision), c->grid, c->block, 0, c->stream, ia);
     if (hipGetLastError() != hipSuccess) {
-        hipFree(c->status);
+        (void)hipFree(c->status);
+        (void)hipFree(c->stats);
         delete c;
         return RLBM_EHIP;
     }
@@ -788,6 +837,7 @@ int rlbm_step(rlbm_ctx *c, int64_t nsteps) {
         c->cur ^= 1;
         c->steps++;
     }
+    if (c->p.collect_stats) c->stat_steps += nsteps;
     return hipGetLastError() == hipSuccess ? RLBM_OK : RLBM_EHIP;
 }
 
@@ -803,6 +853,29 @@ int rlbm_moments(rlbm_ctx *c, const rlbm_out_fields *o) {
     a.o_uy = o->uy;
     a.o_qx = o->qx;
     a.o_qy = o->qy;
+    a.stats = nullptr;
+    hipLaunchKernelGGL(pick(1, c->p.stats, c->p.precision), c->grid, c->block, 0, c->stream, a);
+    if (hipGetLastError() != hipSuccess) return RLBM_EHIP;
+    return rlbm_sync(c);
+}
+
+int rlbm_inversion_stats(rlbm_ctx *c, uint64_t *iterations, uint64_t *solves) {
+    if (!c || !iterations || !solves) return RLBM_EINVAL;
+    unsigned long long h[2] = {0, 0};
+    if (hipMemcpyAsync(h, c->stats, sizeof(h), hipMemcpyDeviceToHost, c->stream) != hipSuccess) return RLBM_EHIP;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return RLBM_EHIP;
+    *iterations = h[0];
+    *solves = (c->p.stats == RLBM_MJ) ? 0 : (uint64_t)c->stat_steps * (uint64_t)c->base.plane;
+    return RLBM_OK;
+}
+
+int rlbm_inversion_samples(rlbm_ctx *c, float *x, float *t) {
+    if (!c || !x || !t) return RLBM_EINVAL;
+    KArgs a = c->base;
+    a.fin = c->cur ? c->p.f_b : c->p.f_a;
+    a.o_mlx = x;
+    a.o_mlt = t;
+    a.stats = nullptr;
     hipLaunchKernelGGL(pick(1, c->p.stats, c->p.precision), c->grid, c->block, 0, c->stream, a);
     if (hipGetLastError() != hipSuccess) return RLBM_EHIP;
     return rlbm_sync(c);
@@ -826,8 +899,8 @@ int rlbm_sync(rlbm_ctx *c) {
     if (hipMemcpyAsync(&h, c->status, sizeof(unsigned), hipMemcpyDeviceToHost, c->stream) != hipSuccess) return RLBM_EHIP;
     if (hipStreamSynchronize(c->stream) != hipSuccess) return RLBM_EHIP;
     if (h) {
-        unsigned zero = 0;
-        if (hipMemcpy(c->status, &zero, sizeof(unsigned), hipMemcpyHostToDevice) != hipSuccess) return RLBM_EHIP;
+        if (hipMemsetAsync(c->status, 0, sizeof(unsigned), c->stream) != hipSuccess) return RLBM_EHIP;
+        if (hipStreamSynchronize(c->stream) != hipSuccess) return RLBM_EHIP;
         return RLBM_EDOMAIN;
     }
     return RLBM_OK;
@@ -835,8 +908,9 @@ int rlbm_sync(rlbm_ctx *c) {
 
 void rlbm_free(rlbm_ctx *c) {
     if (!c) return;
-    hipStreamSynchronize(c->stream);
-    hipFree(c->status);
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipFree(c->status);
+    (void)hipFree(c->stats);
     delete c;
 }
 

@@ -22,6 +22,9 @@ DTYPE = {"fp64": torch.float64, "fp32": torch.float32}
 FIELD_NAMES = ("n", "eps", "theta", "z", "ux", "uy", "qx", "qy")
 
 FLAG_NONPOSITIVE, FLAG_SUPERLUMINAL, FLAG_CONDENSED, FLAG_RANGE, FLAG_NOCONV = 0x1, 0x2, 0x4, 0x8, 0x10
+MLP_HIDDEN = 32
+MLP_FLOATS = 4 + 3 * MLP_HIDDEN + 1
+MLP_NTRAIN = 3 * MLP_HIDDEN + 1
 
 
 class Params(ctypes.Structure):
@@ -30,7 +33,8 @@ class Params(ctypes.Structure):
                 ("tau", ctypes.c_double), ("tau_a", ctypes.c_double), ("tau_b", ctypes.c_double),
                 ("bc", ctypes.c_int32 * 4), ("theta_wall", ctypes.c_double * 2), ("guess", ctypes.c_int32),
                 ("mlp", ctypes.c_void_p), ("f_a", ctypes.c_void_p), ("f_b", ctypes.c_void_p),
-                ("stream", ctypes.c_void_p)]
+                ("stream", ctypes.c_void_p), ("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32),
+                ("collect_stats", ctypes.c_int32)]
 
 
 class InitFields(ctypes.Structure):
@@ -70,6 +74,15 @@ def lib():
         L.rlbm_free.restype = None
         L.rlbm_strerror.argtypes = [ctypes.c_int]
         L.rlbm_strerror.restype = ctypes.c_char_p
+        L.rlbm_inversion_stats.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)]
+        L.rlbm_inversion_samples.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        L.rlbm_mlp_workspace_bytes.argtypes = [ctypes.c_int64]
+        L.rlbm_mlp_workspace_bytes.restype = ctypes.c_uint64
+        vp = ctypes.c_void_p
+        L.rlbm_mlp_init.argtypes = [vp, vp, vp, ctypes.c_int64, vp, vp, vp]
+        L.rlbm_mlp_loss_grad.argtypes = [vp, vp, vp, ctypes.c_int64, vp, vp, vp, vp]
+        L.rlbm_mlp_train.argtypes = [vp, vp, vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_float, vp, vp, vp]
+        L.rlbm_mlp_predict.argtypes = [vp, vp, vp, ctypes.c_int64, vp]
         _LIB = L
     return _LIB
 
@@ -88,7 +101,7 @@ class Sim:
 
     params: dict with keys nx, ny, stats ('MJ'|'FD'|'BE'), precision ('fp64'|'fp32'),
     tau_mode ('const'|'theta'), tau, tau_a, tau_b, bc (xlo, xhi, ylo, yhi names),
-    theta_wall (xlo, xhi), guess ('fixed'|'mlp').  init: dict of (ny, nx) float64
+    theta_wall (xlo, xhi), guess ('fixed'|'mlp'), tile ((tile_x, tile_y), default automatic).  init: dict of (ny, nx) float64
     CUDA tensors theta, ux, uy and either n or z.
     """
 
@@ -107,7 +120,9 @@ class Sim:
                    tau=float(params.get("tau", 1.0)), tau_a=float(params.get("tau_a", 2.0)),
                    tau_b=float(params.get("tau_b", 0.2546)), guess=GUESS[params.get("guess", "fixed")],
                    mlp=_ptr(params.get("mlp")), f_a=_ptr(self.f[0]), f_b=_ptr(self.f[1]),
-                   stream=ctypes.c_void_p(self.stream.cuda_stream))
+                   stream=ctypes.c_void_p(self.stream.cuda_stream),
+                   tile_x=int(params.get("tile", (0, 0))[0]), tile_y=int(params.get("tile", (0, 0))[1]),
+                   collect_stats=int(bool(params.get("collect_stats", False))))
         p.bc[:] = [BC[b] for b in bc]
         p.theta_wall[:] = [float(t) for t in tw]
         self._init_tensors = {k: v.contiguous().to(device=device, dtype=torch.float64) for k, v in init.items()}
@@ -142,6 +157,19 @@ class Sim:
     def sync(self):
         _check(lib().rlbm_sync(self.ctx), "rlbm_sync")
 
+    def inversion_stats(self):
+        it, so = ctypes.c_uint64(), ctypes.c_uint64()
+        _check(lib().rlbm_inversion_stats(self.ctx, ctypes.byref(it), ctypes.byref(so)), "rlbm_inversion_stats")
+        return it.value, so.value
+
+    def inversion_samples(self):
+        """(x, t) float32 tensors (ny, nx): x = ln(2 n^3 / (pi eps^2)), t = ln z."""
+        dev = self.f[0].device
+        x = torch.empty((self.ny, self.nx), dtype=torch.float32, device=dev)
+        t = torch.empty_like(x)
+        _check(lib().rlbm_inversion_samples(self.ctx, _ptr(x), _ptr(t)), "rlbm_inversion_samples")
+        return x, t
+
     def status(self):
         return lib().rlbm_status(self.ctx)
 
@@ -155,3 +183,51 @@ class Sim:
             self.close()
         except Exception:
             pass
+
+
+class GuessNet:
+    """The inversion-guess network: device weights plus training through the
+    library's forward/backward/Adam kernels (rlbm_mlp_* in include/rlbm.h)."""
+
+    def __init__(self, device="cuda", stream=None):
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        self.w = torch.zeros(MLP_FLOATS, dtype=torch.float32, device=device)
+        self._ws = None
+        self._ws_n = 0
+
+    def _workspace(self, n):
+        if self._ws is None or self._ws_n < n:
+            nbytes = lib().rlbm_mlp_workspace_bytes(int(n))
+            self._ws = torch.empty(int(nbytes) // 4 + 1, dtype=torch.float32, device=self.w.device)
+            self._ws_n = n
+        return self._ws
+
+    def _s(self):
+        return ctypes.c_void_p(self.stream.cuda_stream)
+
+    def init(self, x, t, noise):
+        x, t, noise = (v.contiguous().float() for v in (x.reshape(-1), t.reshape(-1), noise.reshape(-1)))
+        assert noise.numel() >= MLP_HIDDEN + 1
+        _check(lib().rlbm_mlp_init(_ptr(self.w), _ptr(x), _ptr(t), x.numel(), _ptr(noise),
+                                   _ptr(self._workspace(x.numel())), self._s()), "rlbm_mlp_init")
+
+    def loss_grad(self, x, t):
+        x, t = x.reshape(-1).contiguous().float(), t.reshape(-1).contiguous().float()
+        grad = torch.empty(MLP_NTRAIN, dtype=torch.float32, device=self.w.device)
+        loss = torch.empty(1, dtype=torch.float32, device=self.w.device)
+        _check(lib().rlbm_mlp_loss_grad(_ptr(self.w), _ptr(x), _ptr(t), x.numel(), _ptr(grad), _ptr(loss),
+                                        _ptr(self._workspace(x.numel())), self._s()), "rlbm_mlp_loss_grad")
+        return loss, grad
+
+    def train(self, x, t, iters, lr):
+        x, t = x.reshape(-1).contiguous().float(), t.reshape(-1).contiguous().float()
+        losses = torch.empty(max(int(iters), 1), dtype=torch.float32, device=self.w.device)
+        _check(lib().rlbm_mlp_train(_ptr(self.w), _ptr(x), _ptr(t), x.numel(), int(iters), float(lr), _ptr(losses),
+                                    _ptr(self._workspace(x.numel())), self._s()), "rlbm_mlp_train")
+        return losses[:iters]
+
+    def predict(self, x):
+        x = x.reshape(-1).contiguous().float()
+        y = torch.empty_like(x)
+        _check(lib().rlbm_mlp_predict(_ptr(self.w), _ptr(x), _ptr(y), x.numel(), self._s()), "rlbm_mlp_predict")
+        return y

@@ -54,6 +54,7 @@ INVALID = [
     dict(nx=1), dict(ny=0), dict(stats=3), dict(order=7), dict(precision=5), dict(tau=0.0),
     dict(tau_mode=1, tau_b=0.0), dict(tau_mode=2), dict(bc=[0, 1, 0, 0]), dict(bc=[0, 0, 2, 2]),
     dict(bc=[2, 2, 0, 0], nx=3), dict(f_a=ctypes.c_void_p(0)), dict(f_b=ctypes.c_void_p(0x1000)),
+    dict(tile_x=48, tile_y=5), dict(tile_x=8, tile_y=32), dict(tile_x=64, tile_y=2),
 ]
 
 
