@@ -113,9 +113,37 @@ typedef struct rlbm_ctx rlbm_ctx;
  * on failure *ctx is NULL.  Errors: RLBM_EINVAL, RLBM_EHIP. */
 int rlbm_init(rlbm_ctx **ctx, const rlbm_params *p, const rlbm_init_fields *init);
 
-/* Enqueue nsteps >= 0 time steps (ping-pong between f_a and f_b).
- * Errors: RLBM_EINVAL (nsteps < 0 or ctx NULL), RLBM_EHIP. */
+/* Several independent grids of uneven sizes in one context: p[g] and init[g] for
+ * g < ngrids, each with its own shape, relaxation time, boundaries and buffers;
+ * stats, precision, order, guess, mlp, stream, tile and collect_stats must agree.
+ * Every step advances all grids with one persistent launch over all their tiles.
+ * Intended for transport-coefficient sweeps.  Errors as rlbm_init. */
+int rlbm_init_batch(rlbm_ctx **ctx, int32_t ngrids, const rlbm_params *p, const rlbm_init_fields *init);
+
+/* Enqueue nsteps >= 0 time steps (ping-pong between f_a and f_b of every grid).
+ * Runs of 64 or more steps replay captured graphs of 32 steps (one graph launch
+ * per 32 steps).  Errors: RLBM_EINVAL (nsteps < 0 or ctx NULL), RLBM_EHIP. */
 int rlbm_step(rlbm_ctx *ctx, int64_t nsteps);
+
+/* Capture the 32-step graphs that rlbm_step replays (for both parities) now, so
+ * that a later timed run does not include capture and instantiation.  Runs no step. */
+int rlbm_capture(rlbm_ctx *ctx);
+
+/* Set the workgroup tile (tile_x * tile_y = 256, tile_x a power of two >= 16) and,
+ * for a batch, the launch mode: persistent > 0 launches that many workgroups per
+ * XCD, each sweeping tiles of its XCD's range; 0 launches one workgroup per tile.
+ * Drops captured graphs.  Errors: RLBM_EINVAL, RLBM_EHIP. */
+int rlbm_configure(rlbm_ctx *ctx, int32_t tile_x, int32_t tile_y, int32_t persistent);
+
+/* Time trial_steps steps with each workgroup tile shape in {32x8, 64x4, 16x16,
+ * 128x2, 256x1} (one workgroup per tile) and, for a batch, also 32x8 and 64x4 with
+ * 96 persistent workgroups per XCD; keep the fastest; the chosen shape is returned.  The trial
+ * steps are real steps of the simulation (they advance the state and the step
+ * count; inversion statistics become unavailable).  Synchronises the stream. */
+int rlbm_autotune(rlbm_ctx *ctx, int32_t trial_steps, int32_t *tile_x, int32_t *tile_y);
+
+/* rlbm_moments for grid g of a batch (g = 0 for a single grid). */
+int rlbm_moments_grid(rlbm_ctx *ctx, int32_t g, const rlbm_out_fields *out);
 
 /* Fields of the current state (moments of the pre-collision populations the next
  * step would see), written to the non-NULL device arrays of out; synchronises the

@@ -23,14 +23,17 @@
 #include <cstdint>
 #include <cstdlib>
 #include <new>
+#include <vector>
 
 #include "rlbm.h"
 #include "rlbm_mlp.h"
 #include "rlbm_tables.h"
 
 #ifndef RLBM_STEP_WAVES_PER_SIMD
-#define RLBM_STEP_WAVES_PER_SIMD 3   // occupancy target of the step kernel (register budget 512/3)
+#define RLBM_STEP_WAVES_PER_SIMD 3   // occupancy target of the FP32 step kernel (register budget 512/3)
 #endif
+// FP64 populations need about twice the registers: no occupancy target (no spills)
+#define RLBM_STEP_BOUNDS(R) __launch_bounds__(256, sizeof(R) == 8 ? 1 : RLBM_STEP_WAVES_PER_SIMD)
 
 namespace {
 
@@ -325,6 +328,14 @@ __device__ __forceinline__ void gvals(double mu, double (&g)[7], unsigned &flags
     }
 }
 
+// Newton on mu = ln z leaves an error C dmu^2 after a step dmu, with C = f''/(2 f')
+// at most 0.5 for FD and about 0.5/|mu| for BE near mu = 0, so a step below this
+// tolerance is applied and ends the solve (no confirming evaluation).
+template <int ST>
+__device__ __forceinline__ double newton_tol(double mu) {
+    return ST == RLBM_BE ? 1e-8 * fmin(1.0, fabs(mu)) : 1e-8;
+}
+
 // Solve h(mu) = g_2^3/g_3^2 = r for mu = ln z (FD, BE), safeguarded Newton.
 template <int ST>
 __device__ __forceinline__ double invert_h(double r, double mu, unsigned &flags, int &iters) {
@@ -348,8 +359,7 @@ __device__ __forceinline__ double invert_h(double r, double mu, unsigned &flags,
         const double h = g[2] * q * q;
         const double F = h - r;
         const double dmu = F / (h * (3.0 * g[1] / g[2] - 2.0 * q));   // dh/dmu = h (3 g1/g2 - 2 g2/g3)
-        const double tol = 1e-12 * fmax(1.0, fabs(mu));
-        if (F == 0.0 || fabs(dmu) <= tol) {   // quadratic convergence: the residual error is O(dmu^2)
+        if (F == 0.0 || fabs(dmu) <= newton_tol<ST>(mu)) {   // the error left after this step is O(dmu^2)
             mu -= (F == 0.0) ? 0.0 : dmu;
             conv = true;
             break;
@@ -386,8 +396,7 @@ __device__ __forceinline__ double invert_g2(double target, unsigned &flags) {
         gvals<ST, 1, 2>(mu, g, flags);
         const double F = g[2] - target;
         const double dmu = F / g[1];            // d g_2 / d mu = g_1
-        const double tol = 1e-12 * fmax(1.0, fabs(mu));
-        if (F == 0.0 || fabs(dmu) <= tol) {
+        if (F == 0.0 || fabs(dmu) <= newton_tol<ST>(mu)) {
             mu -= (F == 0.0) ? 0.0 : dmu;
             conv = true;
             break;
@@ -578,10 +587,9 @@ __device__ __forceinline__ void report(unsigned *status, unsigned flags) {
 }
 
 // ---------------------------------------------------------------- kernels
+// One fused update of cell (x, y) of the grid described by a.
 template <int ST, typename S, typename R>
-__global__ __launch_bounds__(256, RLBM_STEP_WAVES_PER_SIMD) void k_step(KArgs a) {
-    int x, y;
-    if (!cell_of(a, x, y)) return;
+__device__ __forceinline__ void step_cell(const KArgs &a, int x, int y) {
     unsigned flags = 0;
     const bool wall_lo = (a.bc_xlo == RLBM_BC_WALL_T) && x == 0;
     const bool wall_hi = (a.bc_xhi == RLBM_BC_WALL_T) && x == a.nx - 1;
@@ -601,7 +609,7 @@ __global__ __launch_bounds__(256, RLBM_STEP_WAVES_PER_SIMD) void k_step(KArgs a)
             for (int off = 32; off > 0; off >>= 1) it += __shfl_down(it, off, 64);
             if ((threadIdx.x & 63) == 0) atomicAdd(&a.stats[0], it);
         } else {
-            atomicAdd(&a.stats[0], it);   // partial wavefront at the grid edge
+            atomicAdd(&a.stats[0], it);   // partial wavefront at a grid edge
         }
     }
     if (wall_lo || wall_hi) {
@@ -615,6 +623,45 @@ __global__ __launch_bounds__(256, RLBM_STEP_WAVES_PER_SIMD) void k_step(KArgs a)
     }
     store<S, R>((S *)a.fout, a.plane, y * a.nx + x, f);
     report(a.status, flags);
+}
+
+template <int ST, typename S, typename R>
+__global__ RLBM_STEP_BOUNDS(R) void k_step(KArgs a) {
+    int x, y;
+    if (!cell_of(a, x, y)) return;
+    step_cell<ST, S, R>(a, x, y);
+}
+
+// Many grids in one launch.  The tiles of all grids are numbered consecutively
+// (grid g owns tiles tile_base[g] .. tile_base[g+1]-1, tile_grid[t] = g); a
+// persistent set of workgroups sweeps them, XCD k taking the contiguous tile
+// range [k T/8, (k+1) T/8) so neighbouring tiles share that XCD's L2.  descs holds
+// each grid's arguments with in/out buffers for the current parity.
+struct Batch {
+    int ntiles;
+    int per_xcd;        // ceil(ntiles / 8)
+    int groups_per_xcd; // workgroups launched per XCD
+};
+
+template <int ST, typename S, typename R>
+__global__ RLBM_STEP_BOUNDS(R) void k_step_batch(Batch b, const KArgs *__restrict__ descs,
+                                                 const int *__restrict__ tile_grid, const int *__restrict__ tile_base) {
+    const int xcd = blockIdx.x & 7;
+    const int lane_group = blockIdx.x >> 3;
+    const int t_begin = xcd * b.per_xcd;
+    const int t_end = min(t_begin + b.per_xcd, b.ntiles);
+    for (int t = t_begin + lane_group; t < t_end; t += b.groups_per_xcd) {
+        // the grid index is the same for the whole workgroup: keep it (and so every
+        // field of its descriptor and every buffer descriptor) in scalar registers
+        const int g = __builtin_amdgcn_readfirstlane(tile_grid[t]);
+        const KArgs a = descs[g];
+        const int lt = t - __builtin_amdgcn_readfirstlane(tile_base[g]);
+        const int tyi = lt / a.ntx;
+        const int txi = lt - tyi * a.ntx;
+        const int x = txi * a.tx + (int)threadIdx.x % a.tx;
+        const int y = tyi * a.ty + (int)threadIdx.x / a.tx;
+        if (x < a.nx && y < a.ny) step_cell<ST, S, R>(a, x, y);
+    }
 }
 
 template <int ST, typename S, typename R>
@@ -673,12 +720,21 @@ __global__ __launch_bounds__(256) void k_init(KArgs a) {
 // ---------------------------------------------------------------- host side
 using KFn = void (*)(KArgs);
 
+using BFn = void (*)(Batch, const KArgs *, const int *, const int *);
+
 template <int ST>
 struct Kern {
     static KFn step(int prec) { return prec == RLBM_FP64 ? k_step<ST, double, double> : k_step<ST, float, float>; }
+    static BFn batch(int prec) {
+        return prec == RLBM_FP64 ? k_step_batch<ST, double, double> : k_step_batch<ST, float, float>;
+    }
     static KFn mom(int prec) { return prec == RLBM_FP64 ? k_moments<ST, double, double> : k_moments<ST, float, float>; }
     static KFn init(int prec) { return prec == RLBM_FP64 ? k_init<ST, double, double> : k_init<ST, float, float>; }
 };
+
+BFn pick_batch(int st, int prec) {
+    return st == RLBM_MJ ? Kern<RLBM_MJ>::batch(prec) : st == RLBM_FD ? Kern<RLBM_FD>::batch(prec) : Kern<RLBM_BE>::batch(prec);
+}
 
 KFn pick(int which, int st, int prec) {
     switch (st) {
@@ -691,18 +747,30 @@ KFn pick(int which, int st, int prec) {
 }  // namespace
 
 struct rlbm_ctx {
-    rlbm_params p;
-    KArgs base;
+    std::vector<rlbm_params> p;     // per grid
+    std::vector<KArgs> base;        // per grid, without in/out buffers
     hipStream_t stream;
-    unsigned *status;     // device status word
-    unsigned long long *stats;   // device inversion counters (collect_stats)
-    int64_t stat_steps;   // steps launched with counting on
-    int cur;              // 0: f_a holds the state, 1: f_b
+    unsigned *status;               // device status word
+    unsigned long long *stats;      // device inversion counters (collect_stats)
+    int64_t stat_steps;             // steps launched with counting on
+    int cur;                        // 0: f_a holds the state, 1: f_b
     int64_t steps;
-    dim3 grid, block;
+    bool batch;                     // several grids, one persistent launch per step
+    int tx, ty;                     // workgroup tile
+    // batch tables (device): descs[2][ngrids], tile_grid[ntiles], tile_base[ngrids + 1]
+    KArgs *d_descs;
+    int *d_tile_grid, *d_tile_base;
+    int ntiles_total;
+    int batch_groups_per_xcd;
+    int persistent;                 // batch: workgroups per XCD (0: one workgroup per tile)
+    // replay of captured step chunks
+    hipStream_t cap_stream;
+    hipGraphExec_t gexec[2];        // GRAPH_CHUNK steps starting from parity 0 / 1
 };
 
 namespace {
+
+constexpr int GRAPH_CHUNK = 32;     // even: a replay returns to the starting parity
 
 int validate(const rlbm_params *p) {
     if (!p) return RLBM_EINVAL;
@@ -739,14 +807,210 @@ int validate(const rlbm_params *p) {
     return RLBM_OK;
 }
 
-void tile_shape(const rlbm_params *p, int &tx, int &ty) {
-    if (p->tile_x > 0) {
-        tx = p->tile_x;
-        ty = p->tile_y;
+bool valid_init(const rlbm_init_fields *init) {
+    return init && init->theta && init->ux && init->uy && (init->given_z ? init->z != nullptr : init->n != nullptr);
+}
+
+void auto_tile(const rlbm_params &p, int &tx, int &ty) {
+    if (p.tile_x > 0) {
+        tx = p.tile_x;
+        ty = p.tile_y;
         return;
     }
-    ty = p->ny >= 8 ? 8 : (p->ny >= 4 ? 4 : 2);   // 32 x 8 measured fastest on 2048^2 grids
+    ty = p.ny >= 8 ? 8 : (p.ny >= 4 ? 4 : 2);   // 32 x 8 measured fastest on 2048^2 grids
     tx = 256 / ty;
+}
+
+KArgs make_base(const rlbm_params &p, rlbm_ctx *c) {
+    KArgs a{};
+    a.nx = p.nx;
+    a.ny = p.ny;
+    a.plane = (long long)p.nx * p.ny;
+    a.bc_xlo = p.bc[0];
+    a.bc_xhi = p.bc[1];
+    a.bc_ylo = p.bc[2];
+    a.bc_yhi = p.bc[3];
+    a.tau_mode = p.tau_mode;
+    a.tau = p.tau;
+    a.tau_a = p.tau_a;
+    a.tau_b = p.tau_b;
+    a.th_wall_lo = p.theta_wall[0];
+    a.th_wall_hi = p.theta_wall[1];
+    a.guess = p.guess;
+    a.mlp = p.mlp;
+    a.status = c->status;
+    a.stats = p.collect_stats ? c->stats : nullptr;
+    return a;
+}
+
+void set_tiles(KArgs &a, int tx, int ty) {
+    a.tx = tx;
+    a.ty = ty;
+    a.ntx = (a.nx + tx - 1) / tx;
+    a.ntiles = a.ntx * ((a.ny + ty - 1) / ty);
+    a.per_xcd = (a.ntiles + 7) / 8;
+}
+
+void drop_graphs(rlbm_ctx *c) {
+    for (int i = 0; i < 2; ++i)
+        if (c->gexec[i]) {
+            (void)hipGraphExecDestroy(c->gexec[i]);
+            c->gexec[i] = nullptr;
+        }
+}
+
+void release(rlbm_ctx *c) {
+    if (!c) return;
+    drop_graphs(c);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    (void)hipFree(c->status);
+    (void)hipFree(c->stats);
+    (void)hipFree(c->d_descs);
+    (void)hipFree(c->d_tile_grid);
+    (void)hipFree(c->d_tile_base);
+    delete c;
+}
+
+// (Re)build the tile decomposition of every grid and, for a batch, its device tables.
+int configure(rlbm_ctx *c, int tx, int ty) {
+    drop_graphs(c);
+    c->tx = tx;
+    c->ty = ty;
+    for (auto &a : c->base) set_tiles(a, tx, ty);
+    if (!c->batch) return RLBM_OK;
+    const int ng = (int)c->base.size();
+    std::vector<int> tbase(ng + 1, 0);
+    for (int g = 0; g < ng; ++g) tbase[g + 1] = tbase[g] + c->base[g].ntiles;
+    const int T = tbase[ng];
+    std::vector<int> tgrid(T);
+    for (int g = 0; g < ng; ++g)
+        for (int t = tbase[g]; t < tbase[g + 1]; ++t) tgrid[t] = g;
+    std::vector<KArgs> d(2 * ng);
+    for (int par = 0; par < 2; ++par)
+        for (int g = 0; g < ng; ++g) {
+            KArgs a = c->base[g];
+            a.fin = par ? c->p[g].f_b : c->p[g].f_a;
+            a.fout = par ? c->p[g].f_a : c->p[g].f_b;
+            d[par * ng + g] = a;
+        }
+    (void)hipFree(c->d_tile_grid);
+    c->d_tile_grid = nullptr;
+    if (hipMalloc(&c->d_tile_grid, sizeof(int) * T) != hipSuccess) return RLBM_EHIP;
+    if (!c->d_descs && hipMalloc(&c->d_descs, sizeof(KArgs) * 2 * ng) != hipSuccess) return RLBM_EHIP;
+    if (!c->d_tile_base && hipMalloc(&c->d_tile_base, sizeof(int) * (ng + 1)) != hipSuccess) return RLBM_EHIP;
+    if (hipMemcpyAsync(c->d_tile_grid, tgrid.data(), sizeof(int) * T, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+        hipMemcpyAsync(c->d_tile_base, tbase.data(), sizeof(int) * (ng + 1), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+        hipMemcpyAsync(c->d_descs, d.data(), sizeof(KArgs) * 2 * ng, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+        return RLBM_EHIP;
+    c->ntiles_total = T;
+    // persistent: c->persistent workgroups per XCD sweep its tile range; 0: one per tile
+    const int per_xcd = (T + 7) / 8;
+    c->batch_groups_per_xcd = (c->persistent > 0 && c->persistent < per_xcd) ? c->persistent : per_xcd;
+    return RLBM_OK;
+}
+
+int launch_step(rlbm_ctx *c, hipStream_t s) {
+    const rlbm_params &p0 = c->p[0];
+    if (c->batch) {
+        Batch b;
+        b.ntiles = c->ntiles_total;
+        b.per_xcd = (c->ntiles_total + 7) / 8;
+        b.groups_per_xcd = c->batch_groups_per_xcd;
+        const KArgs *descs = c->d_descs + (size_t)c->cur * c->base.size();
+        hipLaunchKernelGGL(pick_batch(p0.stats, p0.precision), dim3(8 * b.groups_per_xcd), dim3(256), 0, s, b, descs,
+                           (const int *)c->d_tile_grid, (const int *)c->d_tile_base);
+    } else {
+        KArgs a = c->base[0];
+        a.fin = c->cur ? p0.f_b : p0.f_a;
+        a.fout = c->cur ? p0.f_a : p0.f_b;
+        hipLaunchKernelGGL(pick(0, p0.stats, p0.precision), dim3(8 * a.per_xcd), dim3(256), 0, s, a);
+    }
+    c->cur ^= 1;
+    c->steps++;
+    return hipGetLastError() == hipSuccess ? RLBM_OK : RLBM_EHIP;
+}
+
+// Capture GRAPH_CHUNK steps starting at the current parity into an executable graph.
+int capture_chunk(rlbm_ctx *c, hipGraphExec_t &out) {
+    if (!c->cap_stream && hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess)
+        return RLBM_EHIP;
+    const int cur0 = c->cur;
+    const int64_t steps0 = c->steps;
+    if (hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return RLBM_EHIP;
+    int rc = RLBM_OK;
+    for (int i = 0; i < GRAPH_CHUNK && rc == RLBM_OK; ++i) rc = launch_step(c, c->cap_stream);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
+    c->cur = cur0;          // capturing ran nothing
+    c->steps = steps0;
+    if (rc != RLBM_OK || e != hipSuccess || !graph) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return RLBM_EHIP;
+    }
+    const hipError_t ei = hipGraphInstantiate(&out, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    return ei == hipSuccess ? RLBM_OK : RLBM_EHIP;
+}
+
+int finish_init(rlbm_ctx *c, const rlbm_init_fields *init) {
+    const rlbm_params &p0 = c->p[0];
+    for (size_t g = 0; g < c->base.size(); ++g) {
+        KArgs ia = c->base[g];
+        set_tiles(ia, 32, 8);
+        ia.fout = c->p[g].f_a;
+        ia.i_n = init[g].n;
+        ia.i_z = init[g].z;
+        ia.i_theta = init[g].theta;
+        ia.i_ux = init[g].ux;
+        ia.i_uy = init[g].uy;
+        ia.given_z = init[g].given_z;
+        hipLaunchKernelGGL(pick(2, p0.stats, p0.precision), dim3(8 * ia.per_xcd), dim3(256), 0, c->stream, ia);
+    }
+    return hipGetLastError() == hipSuccess ? RLBM_OK : RLBM_EHIP;
+}
+
+int create(rlbm_ctx **out, int ngrids, const rlbm_params *p, const rlbm_init_fields *init) {
+    if (!out) return RLBM_EINVAL;
+    *out = nullptr;
+    if (ngrids < 1 || !p || !init) return RLBM_EINVAL;
+    for (int g = 0; g < ngrids; ++g) {
+        int rc = validate(&p[g]);
+        if (rc) return rc;
+        if (!valid_init(&init[g])) return RLBM_EINVAL;
+        const rlbm_params &a = p[g], &b = p[0];
+        if (a.stats != b.stats || a.precision != b.precision || a.order != b.order || a.guess != b.guess ||
+            a.mlp != b.mlp || a.stream != b.stream || a.tile_x != b.tile_x || a.tile_y != b.tile_y ||
+            a.collect_stats != b.collect_stats)
+            return RLBM_EINVAL;
+    }
+    rlbm_ctx *c = new (std::nothrow) rlbm_ctx();
+    if (!c) return RLBM_EHIP;
+    c->stream = (hipStream_t)p[0].stream;
+    c->batch = ngrids > 1;
+    if (hipMalloc(&c->status, sizeof(unsigned)) != hipSuccess ||
+        hipMalloc(&c->stats, 2 * sizeof(unsigned long long)) != hipSuccess ||
+        hipMemsetAsync(c->status, 0, sizeof(unsigned), c->stream) != hipSuccess ||
+        hipMemsetAsync(c->stats, 0, 2 * sizeof(unsigned long long), c->stream) != hipSuccess) {
+        release(c);
+        return RLBM_EHIP;
+    }
+    c->p.assign(p, p + ngrids);
+    for (int g = 0; g < ngrids; ++g) c->base.push_back(make_base(p[g], c));
+    int tx, ty;
+    auto_tile(p[0], tx, ty);
+    if (c->batch && p[0].tile_x == 0) {
+        tx = 32;
+        ty = 8;
+    }
+    int rc = configure(c, tx, ty);
+    if (!rc) rc = finish_init(c, init);
+    if (rc) {
+        release(c);
+        return rc;
+    }
+    *out = c;
+    return RLBM_OK;
 }
 
 }  // namespace
@@ -754,97 +1018,110 @@ void tile_shape(const rlbm_params *p, int &tx, int &ty) {
 extern "C" {
 
 int rlbm_init(rlbm_ctx **out, const rlbm_params *p, const rlbm_init_fields *init) {
-    if (!out) return RLBM_EINVAL;
-    *out = nullptr;
-    int rc = validate(p);
-    if (rc) return rc;
-    if (!init || !init->theta || !init->ux || !init->uy || (init->given_z ? !init->z : !init->n)) return RLBM_EINVAL;
-    rlbm_ctx *c = new (std::nothrow) rlbm_ctx();
-    if (!c) return RLBM_EHIP;
-    c->p = *p;
-    c->stream = (hipStream_t)p->stream;
-    if (hipMalloc(&c->status, sizeof(unsigned)) != hipSuccess) {
-        delete c;
-        return RLBM_EHIP;
-    }
-    if (hipMalloc(&c->stats, 2 * sizeof(unsigned long long)) != hipSuccess) {
-        (void)hipFree(c->status);
-        delete c;
-        return RLBM_EHIP;
-    }
-    if (hipMemsetAsync(c->status, 0, sizeof(unsigned), c->stream) != hipSuccess ||
-        hipMemsetAsync(c->stats, 0, 2 * sizeof(unsigned long long), c->stream) != hipSuccess) {
-        (void)hipFree(c->status);
-        (void)hipFree(c->stats);
-        delete c;
-        return RLBM_EHIP;
-    }
-    c->stat_steps = 0;
-    KArgs &a = c->base;
-    a = KArgs{};
-    a.nx = p->nx;
-    a.ny = p->ny;
-    a.plane = (long long)p->nx * p->ny;
-    tile_shape(p, a.tx, a.ty);
-    a.ntx = (p->nx + a.tx - 1) / a.tx;
-    a.ntiles = a.ntx * ((p->ny + a.ty - 1) / a.ty);
-    a.per_xcd = (a.ntiles + 7) / 8;
-    a.bc_xlo = p->bc[0];
-    a.bc_xhi = p->bc[1];
-    a.bc_ylo = p->bc[2];
-    a.bc_yhi = p->bc[3];
-    a.tau_mode = p->tau_mode;
-    a.tau = p->tau;
-    a.tau_a = p->tau_a;
-    a.tau_b = p->tau_b;
-    a.th_wall_lo = p->theta_wall[0];
-    a.th_wall_hi = p->theta_wall[1];
-    a.guess = p->guess;
-    a.mlp = p->mlp;
-    a.status = c->status;
-    a.stats = p->collect_stats ? c->stats : nullptr;
-    c->grid = dim3(8 * a.per_xcd);
-    c->block = dim3(256);
-    c->cur = 0;
-    c->steps = 0;
-    KArgs ia = a;
-    ia.fout = p->f_a;
-    ia.i_n = init->n;
-    ia.i_z = init->z;
-    ia.i_theta = init->theta;
-    ia.i_ux = init->ux;
-    ia.i_uy = init->uy;
-    ia.given_z = init->given_z;
-    hipLaunchKernelGGL(pick(2, p->stats, p->precision), c->grid, c->block, 0, c->stream, ia);
-    if (hipGetLastError() != hipSuccess) {
-        (void)hipFree(c->status);
-        (void)hipFree(c->stats);
-        delete c;
-        return RLBM_EHIP;
-    }
-    *out = c;
-    return RLBM_OK;
+    return create(out, 1, p, init);
+}
+
+int rlbm_init_batch(rlbm_ctx **out, int32_t ngrids, const rlbm_params *p, const rlbm_init_fields *init) {
+    return create(out, ngrids, p, init);
 }
 
 int rlbm_step(rlbm_ctx *c, int64_t nsteps) {
     if (!c || nsteps < 0) return RLBM_EINVAL;
-    KFn fn = pick(0, c->p.stats, c->p.precision);
-    for (int64_t i = 0; i < nsteps; ++i) {
-        KArgs a = c->base;
-        a.fin = c->cur ? c->p.f_b : c->p.f_a;
-        a.fout = c->cur ? c->p.f_a : c->p.f_b;
-        hipLaunchKernelGGL(fn, c->grid, c->block, 0, c->stream, a);
-        c->cur ^= 1;
-        c->steps++;
+    int64_t left = nsteps;
+    if (left >= 2 * GRAPH_CHUNK) {
+        // replay captured chunks: one graph launch per GRAPH_CHUNK steps
+        hipGraphExec_t &g = c->gexec[c->cur];
+        if (!g) {
+            int rc = capture_chunk(c, g);
+            if (rc) return rc;
+        }
+        for (; left >= GRAPH_CHUNK; left -= GRAPH_CHUNK) {
+            if (hipGraphLaunch(g, c->stream) != hipSuccess) return RLBM_EHIP;
+            c->steps += GRAPH_CHUNK;
+        }
     }
-    if (c->p.collect_stats) c->stat_steps += nsteps;
-    return hipGetLastError() == hipSuccess ? RLBM_OK : RLBM_EHIP;
+    for (; left > 0; --left) {
+        int rc = launch_step(c, c->stream);
+        if (rc) return rc;
+    }
+    if (c->p[0].collect_stats) c->stat_steps += nsteps;
+    return RLBM_OK;
 }
 
-int rlbm_moments(rlbm_ctx *c, const rlbm_out_fields *o) {
-    if (!c || !o) return RLBM_EINVAL;
-    KArgs a = c->base;
-    a.fin = c->cur ? c->p.f_b : c->p.f_a;
+int rlbm_capture(rlbm_ctx *c) {
+    if (!c) return RLBM_EINVAL;
+    const int cur0 = c->cur;
+    for (int par = 0; par < 2; ++par) {
+        c->cur = par;
+        if (!c->gexec[par]) {
+            int rc = capture_chunk(c, c->gexec[par]);
+            if (rc) {
+                c->cur = cur0;
+                return rc;
+            }
+        }
+    }
+    c->cur = cur0;
+    return RLBM_OK;
+}
+
+int rlbm_configure(rlbm_ctx *c, int32_t tile_x, int32_t tile_y, int32_t persistent) {
+    if (!c || tile_x < 16 || tile_y < 1 || tile_x * tile_y != 256 || (tile_x & (tile_x - 1)) || persistent < 0)
+        return RLBM_EINVAL;
+    c->persistent = persistent;
+    return configure(c, tile_x, tile_y);
+}
+
+int rlbm_autotune(rlbm_ctx *c, int32_t trial_steps, int32_t *tile_x, int32_t *tile_y) {
+    if (!c || trial_steps < 1) return RLBM_EINVAL;
+    static const int cand[][3] = {{32, 8, 0}, {64, 4, 0}, {16, 16, 0}, {128, 2, 0}, {256, 1, 0},
+                                  {32, 8, 96}, {64, 4, 96}};
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return RLBM_EHIP;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return RLBM_EHIP;
+    }
+    float best = 1e30f;
+    int bx = c->tx, by = c->ty, bp = c->persistent, rc = RLBM_OK;
+    for (const auto &t : cand) {
+        if (t[2] && !c->batch) continue;
+        c->persistent = t[2];
+        rc = configure(c, t[0], t[1]);
+        if (rc) break;
+        rc = launch_step(c, c->stream);   // warm-up
+        if (rc) break;
+        (void)hipEventRecord(e0, c->stream);
+        for (int i = 0; i < trial_steps && rc == RLBM_OK; ++i) rc = launch_step(c, c->stream);
+        (void)hipEventRecord(e1, c->stream);
+        if (rc || hipEventSynchronize(e1) != hipSuccess) {
+            rc = rc ? rc : RLBM_EHIP;
+            break;
+        }
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best) {
+            best = ms;
+            bx = t[0];
+            by = t[1];
+            bp = t[2];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (c->p[0].collect_stats) c->stat_steps = -1;   // counters mixed with trial steps: invalid
+    c->persistent = bp;
+    if (!rc) rc = configure(c, bx, by);
+    if (tile_x) *tile_x = bx;
+    if (tile_y) *tile_y = by;
+    return rc;
+}
+
+int rlbm_moments_grid(rlbm_ctx *c, int32_t g, const rlbm_out_fields *o) {
+    if (!c || !o || g < 0 || g >= (int)c->base.size()) return RLBM_EINVAL;
+    KArgs a = c->base[g];
+    set_tiles(a, 32, 8);
+    a.fin = c->cur ? c->p[g].f_b : c->p[g].f_a;
     a.o_n = o->n;
     a.o_eps = o->eps;
     a.o_theta = o->theta;
@@ -854,7 +1131,7 @@ int rlbm_moments(rlbm_ctx *c, const rlbm_out_fields *o) {
     a.o_qx = o->qx;
     a.o_qy = o->qy;
     a.stats = nullptr;
-    hipLaunchKernelGGL(pick(1, c->p.stats, c->p.precision), c->grid, c->block, 0, c->stream, a);
+    hipLaunchKernelGGL(pick(1, c->p[0].stats, c->p[0].precision), dim3(8 * a.per_xcd), dim3(256), 0, c->stream, a);
     if (hipGetLastError() != hipSuccess) return RLBM_EHIP;
     return rlbm_sync(c);
 }
@@ -864,22 +1141,28 @@ int rlbm_inversion_stats(rlbm_ctx *c, uint64_t *iterations, uint64_t *solves) {
     unsigned long long h[2] = {0, 0};
     if (hipMemcpyAsync(h, c->stats, sizeof(h), hipMemcpyDeviceToHost, c->stream) != hipSuccess) return RLBM_EHIP;
     if (hipStreamSynchronize(c->stream) != hipSuccess) return RLBM_EHIP;
+    if (c->stat_steps < 0) return RLBM_EINVAL;   // autotune trial steps were mixed in
+    uint64_t cells = 0;
+    for (const auto &a : c->base) cells += (uint64_t)a.plane;
     *iterations = h[0];
-    *solves = (c->p.stats == RLBM_MJ) ? 0 : (uint64_t)c->stat_steps * (uint64_t)c->base.plane;
+    *solves = (c->p[0].stats == RLBM_MJ) ? 0 : (uint64_t)c->stat_steps * cells;
     return RLBM_OK;
 }
 
 int rlbm_inversion_samples(rlbm_ctx *c, float *x, float *t) {
     if (!c || !x || !t) return RLBM_EINVAL;
-    KArgs a = c->base;
-    a.fin = c->cur ? c->p.f_b : c->p.f_a;
+    KArgs a = c->base[0];
+    set_tiles(a, 32, 8);
+    a.fin = c->cur ? c->p[0].f_b : c->p[0].f_a;
     a.o_mlx = x;
     a.o_mlt = t;
     a.stats = nullptr;
-    hipLaunchKernelGGL(pick(1, c->p.stats, c->p.precision), c->grid, c->block, 0, c->stream, a);
+    hipLaunchKernelGGL(pick(1, c->p[0].stats, c->p[0].precision), dim3(8 * a.per_xcd), dim3(256), 0, c->stream, a);
     if (hipGetLastError() != hipSuccess) return RLBM_EHIP;
     return rlbm_sync(c);
 }
+
+int rlbm_moments(rlbm_ctx *c, const rlbm_out_fields *o) { return rlbm_moments_grid(c, 0, o); }
 
 int rlbm_state_index(const rlbm_ctx *c) { return c ? c->cur : -1; }
 
@@ -909,9 +1192,7 @@ int rlbm_sync(rlbm_ctx *c) {
 void rlbm_free(rlbm_ctx *c) {
     if (!c) return;
     (void)hipStreamSynchronize(c->stream);
-    (void)hipFree(c->status);
-    (void)hipFree(c->stats);
-    delete c;
+    release(c);
 }
 
 const char *rlbm_strerror(int code) {

@@ -74,6 +74,13 @@ def lib():
         L.rlbm_free.restype = None
         L.rlbm_strerror.argtypes = [ctypes.c_int]
         L.rlbm_strerror.restype = ctypes.c_char_p
+        L.rlbm_init_batch.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, ctypes.POINTER(Params),
+                                      ctypes.POINTER(InitFields)]
+        L.rlbm_autotune.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                    ctypes.POINTER(ctypes.c_int32)]
+        L.rlbm_capture.argtypes = [ctypes.c_void_p]
+        L.rlbm_configure.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+        L.rlbm_moments_grid.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(OutFields)]
         L.rlbm_inversion_stats.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)]
         L.rlbm_inversion_samples.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         L.rlbm_mlp_workspace_bytes.argtypes = [ctypes.c_int64]
@@ -96,6 +103,29 @@ def _check(code, what):
         raise RlbmError(code, what)
 
 
+def _grid_args(params, init, device, stream):
+    """Population buffers, rlbm_params and rlbm_init_fields for one grid."""
+    nx, ny = int(params["nx"]), int(params["ny"])
+    prec = params.get("precision", "fp64")
+    f = [torch.empty((72, ny, nx), dtype=DTYPE[prec], device=device) for _ in range(2)]
+    bc = params.get("bc", ("periodic",) * 4)
+    tw = params.get("theta_wall", (1.0, 1.0))
+    p = Params(nx=nx, ny=ny, stats=STATS[params.get("stats", "MJ")], order=int(params.get("order", 5)),
+               precision=PRECISION[prec], tau_mode=TAU_MODE[params.get("tau_mode", "const")],
+               tau=float(params.get("tau", 1.0)), tau_a=float(params.get("tau_a", 2.0)),
+               tau_b=float(params.get("tau_b", 0.2546)), guess=GUESS[params.get("guess", "fixed")],
+               mlp=_ptr(params.get("mlp")), f_a=_ptr(f[0]), f_b=_ptr(f[1]),
+               stream=ctypes.c_void_p(stream.cuda_stream),
+               tile_x=int(params.get("tile", (0, 0))[0]), tile_y=int(params.get("tile", (0, 0))[1]),
+               collect_stats=int(bool(params.get("collect_stats", False))))
+    p.bc[:] = [BC[b] for b in bc]
+    p.theta_wall[:] = [float(t) for t in tw]
+    keep = {k: v.contiguous().to(device=device, dtype=torch.float64) for k, v in init.items()}
+    fi = InitFields(n=_ptr(keep.get("n")), z=_ptr(keep.get("z")), theta=_ptr(keep["theta"]), ux=_ptr(keep["ux"]),
+                    uy=_ptr(keep["uy"]), given_z=int("z" in keep))
+    return f, p, fi, keep
+
+
 class Sim:
     """One grid: owns two population tensors (ping-pong) on the current CUDA/HIP device.
 
@@ -106,34 +136,23 @@ class Sim:
     """
 
     def __init__(self, params, init, device="cuda", stream=None):
-        L = lib()
-        self.params = dict(params)
-        nx, ny = int(params["nx"]), int(params["ny"])
-        prec = params.get("precision", "fp64")
-        self.nx, self.ny, self.precision = nx, ny, prec
         self.stream = stream if stream is not None else torch.cuda.current_stream(device)
-        self.f = [torch.empty((72, ny, nx), dtype=DTYPE[prec], device=device) for _ in range(2)]
-        bc = params.get("bc", ("periodic",) * 4)
-        tw = params.get("theta_wall", (1.0, 1.0))
-        p = Params(nx=nx, ny=ny, stats=STATS[params.get("stats", "MJ")], order=int(params.get("order", 5)),
-                   precision=PRECISION[prec], tau_mode=TAU_MODE[params.get("tau_mode", "const")],
-                   tau=float(params.get("tau", 1.0)), tau_a=float(params.get("tau_a", 2.0)),
-                   tau_b=float(params.get("tau_b", 0.2546)), guess=GUESS[params.get("guess", "fixed")],
-                   mlp=_ptr(params.get("mlp")), f_a=_ptr(self.f[0]), f_b=_ptr(self.f[1]),
-                   stream=ctypes.c_void_p(self.stream.cuda_stream),
-                   tile_x=int(params.get("tile", (0, 0))[0]), tile_y=int(params.get("tile", (0, 0))[1]),
-                   collect_stats=int(bool(params.get("collect_stats", False))))
-        p.bc[:] = [BC[b] for b in bc]
-        p.theta_wall[:] = [float(t) for t in tw]
-        self._init_tensors = {k: v.contiguous().to(device=device, dtype=torch.float64) for k, v in init.items()}
-        it = self._init_tensors
-        given_z = "z" in it
-        fi = InitFields(n=_ptr(it.get("n")), z=_ptr(it.get("z")), theta=_ptr(it["theta"]), ux=_ptr(it["ux"]),
-                        uy=_ptr(it["uy"]), given_z=int(given_z))
-        self._p = p
+        self.nx, self.ny = int(params["nx"]), int(params["ny"])
+        self.precision = params.get("precision", "fp64")
+        self.params = dict(params)
+        self.f, self._p, self._fi, self._keep = _grid_args(params, init, device, self.stream)
         ctx = ctypes.c_void_p()
-        _check(L.rlbm_init(ctypes.byref(ctx), ctypes.byref(p), ctypes.byref(fi)), "rlbm_init")
+        _check(lib().rlbm_init(ctypes.byref(ctx), ctypes.byref(self._p), ctypes.byref(self._fi)), "rlbm_init")
         self.ctx = ctx
+
+    def capture(self):
+        """Capture the replayed step graphs now (no step is run)."""
+        _check(lib().rlbm_capture(self.ctx), "rlbm_capture")
+
+    def autotune(self, trial_steps=5):
+        tx, ty = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().rlbm_autotune(self.ctx, int(trial_steps), ctypes.byref(tx), ctypes.byref(ty)), "rlbm_autotune")
+        return tx.value, ty.value
 
     def step(self, nsteps=1):
         _check(lib().rlbm_step(self.ctx, int(nsteps)), "rlbm_step")
@@ -231,3 +250,75 @@ class GuessNet:
         y = torch.empty_like(x)
         _check(lib().rlbm_mlp_predict(_ptr(self.w), _ptr(x), _ptr(y), x.numel(), self._s()), "rlbm_mlp_predict")
         return y
+
+
+class Batch:
+    """Many grids of uneven sizes advanced by one launch per step (rlbm_init_batch).
+
+    params_list / init_list: one params dict and init-field dict per grid (as for Sim);
+    statistic, precision, guess and tile must agree across grids."""
+
+    def __init__(self, params_list, init_list, device="cuda", stream=None):
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        args = [_grid_args(p, i, device, self.stream) for p, i in zip(params_list, init_list)]
+        self.params = [dict(p) for p in params_list]
+        self.f = [a[0] for a in args]
+        self._keep = [a[3] for a in args]
+        n = len(args)
+        self._p = (Params * n)(*[a[1] for a in args])
+        self._fi = (InitFields * n)(*[a[2] for a in args])
+        ctx = ctypes.c_void_p()
+        _check(lib().rlbm_init_batch(ctypes.byref(ctx), n, self._p, self._fi), "rlbm_init_batch")
+        self.ctx = ctx
+
+    def __len__(self):
+        return len(self.f)
+
+    def step(self, nsteps=1):
+        _check(lib().rlbm_step(self.ctx, int(nsteps)), "rlbm_step")
+
+    def capture(self):
+        """Capture the replayed step graphs now (no step is run)."""
+        _check(lib().rlbm_capture(self.ctx), "rlbm_capture")
+
+    def autotune(self, trial_steps=5):
+        tx, ty = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().rlbm_autotune(self.ctx, int(trial_steps), ctypes.byref(tx), ctypes.byref(ty)), "rlbm_autotune")
+        return tx.value, ty.value
+
+    def configure(self, tile_x, tile_y, persistent=0):
+        _check(lib().rlbm_configure(self.ctx, int(tile_x), int(tile_y), int(persistent)), "rlbm_configure")
+
+    def state(self, g):
+        return self.f[g][lib().rlbm_state_index(self.ctx)]
+
+    @property
+    def steps_done(self):
+        return lib().rlbm_steps_done(self.ctx)
+
+    def fields(self, g, names=FIELD_NAMES, check=True):
+        p = self.params[g]
+        ny, nx = int(p["ny"]), int(p["nx"])
+        out = {k: torch.empty((ny, nx), dtype=torch.float64, device=self.f[g][0].device) for k in names}
+        of = OutFields(**{k: _ptr(out.get(k)) for k in FIELD_NAMES})
+        rc = lib().rlbm_moments_grid(self.ctx, int(g), ctypes.byref(of))
+        if check:
+            _check(rc, "rlbm_moments_grid")
+        return out
+
+    def sync(self):
+        _check(lib().rlbm_sync(self.ctx), "rlbm_sync")
+
+    def status(self):
+        return lib().rlbm_status(self.ctx)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            lib().rlbm_free(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
