@@ -154,7 +154,7 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="fd_hotspot_2048", choices=sorted(WORKLOADS))
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "f16dev"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile", default="auto", help="workgroup tile TXxTY (e.g. 64x4) or auto")
     ap.add_argument("--guess", default="fixed", choices=["fixed", "mlp"],
@@ -212,8 +212,8 @@ def main():
     ms = e0.elapsed_time(e1)
     status = sim.status()
     mlups = ncell * args.steps / (ms * 1e-3) / 1e6
-    elem = 8 if args.precision == "fp64" else 4
-    bytes_per_launch = 2 * 72 * elem * ncell
+    cell_bytes = {"fp64": 72 * 8, "fp32": 72 * 4, "f16dev": 180}[args.precision]
+    bytes_per_launch = 2 * cell_bytes * ncell
     launch_s = ms * 1e-3 / args.steps
     achieved = bytes_per_launch / launch_s / 1e9
     sim.close()
@@ -230,7 +230,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.precision == "fp32" else "f64",
+        "dtype": {"fp32": "f32", "fp64": "f64", "f16dev": "f16 deviations, f32 arithmetic"}[args.precision],
         "data": "synthetic",
         "config": {"workload": args.workload, "description": WORKLOADS[args.workload],
                    "grid": [params["nx"], params["ny"]] if "grids" not in params else None,

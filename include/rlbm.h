@@ -16,8 +16,8 @@
  *  - Populations: structure of arrays f[q][y][x], q = 6*n + k with direction
  *    n = 0..11 (angle n*pi/6; the paper's label i = n + 1) and radial shell
  *    k = 0..5; cell (x, y) at integer coordinates, x fastest.  The element type
- *    is double (RLBM_FP64) or float (RLBM_FP32).  Each population buffer holds
- *    72*nx*ny elements.
+ *    is double (RLBM_FP64) or float (RLBM_FP32): 72*nx*ny elements per buffer;
+ *    RLBM_F16DEV buffers hold 180*nx*ny bytes (layout at enum rlbm_precision).
  *  - The stored state is the post-collision population.  One step is: pull
  *    streaming, moments N^mu and T^{mu nu}, Landau frame (Eq. eigen-eq), density
  *    (Eq. density-eq), inversion to (theta, z), relaxation time, fifth-order
@@ -59,7 +59,13 @@ enum rlbm_status_code {
 };
 
 enum rlbm_stats { RLBM_MJ = 0, RLBM_FD = 1, RLBM_BE = 2 };         /* Eqs. mj-w-eq, fd-w-eq, be-w-eq */
-enum rlbm_precision { RLBM_FP64 = 0, RLBM_FP32 = 1 };
+/* Population storage.  RLBM_F16DEV (project extension): per cell the deviations
+ * e_i = (f_i / w_k - R_i) / s as IEEE half, R_{k,n} = rho_k + p_k (alpha cos phi_n
+ * + beta sin phi_n) (direction average of f/w per shell plus a least-squares
+ * p-weighted dipole), s = max_i |f_i / w_k - R_i|; a buffer holds 72 half planes
+ * (q = 6 n + k) followed by 9 float planes rho_0..rho_5, alpha, beta, s: 180 bytes
+ * per cell.  Arithmetic as RLBM_FP32. */
+enum rlbm_precision { RLBM_FP64 = 0, RLBM_FP32 = 1, RLBM_F16DEV = 2 };
 enum rlbm_tau_mode { RLBM_TAU_CONST = 0, RLBM_TAU_INV_THETA = 1 };  /* tau, or tau_a/theta + tau_b */
 enum rlbm_bc {
     RLBM_BC_PERIODIC = 0, /* wrap (both sides of an axis must be periodic) */
@@ -87,7 +93,8 @@ typedef struct rlbm_params {
     double theta_wall[2];    /* wall temperature of the x-low and x-high sides */
     int32_t guess;           /* rlbm_guess */
     const float *mlp;        /* device pointer to the MLP weights (RLBM_GUESS_MLP), else NULL */
-    void *f_a, *f_b;         /* device population buffers (ping-pong), 72*nx*ny elements each */
+    void *f_a, *f_b;         /* device population buffers (ping-pong), 72*nx*ny elements each
+                                (F16DEV: 180*nx*ny bytes each, 4-byte aligned) */
     void *stream;            /* hipStream_t, NULL = default stream */
     int32_t tile_x, tile_y;  /* cells per workgroup tile, tile_x * tile_y = 256 with tile_x a power
                                 of two >= 16; 0, 0 = automatic (32 x 8; 64 x 4 or 128 x 2 for ny < 8, 4) */

@@ -23,6 +23,7 @@
 #include <cstdint>
 #include <cstdlib>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "rlbm.h"
@@ -33,7 +34,9 @@
 #define RLBM_STEP_WAVES_PER_SIMD 3   // occupancy target of the FP32 step kernel (register budget 512/3)
 #endif
 // FP64 populations need about twice the registers: no occupancy target (no spills)
-#define RLBM_STEP_BOUNDS(R) __launch_bounds__(256, sizeof(R) == 8 ? 1 : RLBM_STEP_WAVES_PER_SIMD)
+// FD/BE carry the inversion's FP64 state as well: 2 waves per SIMD avoids spills
+#define RLBM_STEP_BOUNDS(ST, R) \
+    __launch_bounds__(256, sizeof(R) == 8 ? 1 : ((ST) == RLBM_MJ ? RLBM_STEP_WAVES_PER_SIMD : 2))
 
 namespace {
 
@@ -582,6 +585,154 @@ __device__ __forceinline__ void store(S *__restrict__ fout, long long plane, int
     }
 }
 
+// ---------------------------------------------------------------- FP16 deviation storage
+// Per cell: e_i = (f_i / w_k - R_i) / s stored as IEEE half, with the reference
+// R_{k,n} = rho_k + p_k (alpha cos phi_n + beta sin phi_n) (the direction average of
+// f/w per shell plus one p-weighted dipole, least squares) and the scale
+// s = max_i |f_i / w_k - R_i|.  Buffer layout: 72 half planes (q = 6 n + k), then 9
+// float planes rho_0..rho_5, alpha, beta, s.  The reference is linear in the side
+// values, so a pull interpolates the side values with the bilinear weights and the
+// deviations with the weights times the source scales.
+struct Dev16 {};
+
+__device__ __forceinline__ float half_bits_to_float(unsigned short h) {
+    return (float)__builtin_bit_cast(_Float16, h);
+}
+
+struct SideRef {
+    float v[9];   // rho_0..rho_5, alpha, beta, s
+};
+
+__device__ __forceinline__ void load_side(rsrc_t rs, unsigned cell, unsigned pb4, SideRef &o) {
+#pragma unroll
+    for (int j = 0; j < 9; ++j) o.v[j] = bload<float>(rs, cell * 4u, (unsigned)j * pb4);
+}
+
+// One direction n with taps (cell offset, weight, side values).
+template <int ST, int N, int NT>
+__device__ __forceinline__ void dev_direction(const char *base, long long plane, const unsigned (&cell)[NT],
+                                              const float (&wt)[NT], const SideRef *const (&sd)[NT], float (&f)[72]) {
+    const unsigned pb2 = (unsigned)plane * 2u;
+    const rsrc_t r = make_rsrc(base + (long long)(6 * N) * plane * 2, 6u * pb2);
+    float rb[6], ab = 0.0f, bb = 0.0f, ws[NT];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) rb[k] = 0.0f;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) rb[k] += wt[t] * sd[t]->v[k];
+        ab += wt[t] * sd[t]->v[6];
+        bb += wt[t] * sd[t]->v[7];
+        ws[t] = wt[t] * sd[t]->v[8];
+    }
+    const float tn = ab * (float)cdir(N) + bb * (float)sdir(N);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        float acc = rb[k] + (float)P_SHELL[ST][k] * tn;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const unsigned short h =
+                __builtin_amdgcn_raw_buffer_load_b16(r, cell[t] * 2u, (unsigned)k * pb2, 0);
+            acc += ws[t] * half_bits_to_float(h);
+        }
+        f[6 * N + k] = (float)W_SHELL[ST][k] * acc;
+    }
+}
+
+template <int ST>
+__device__ __forceinline__ void pull_dev(const void *fin, long long plane, int nx, int x, int y, int xl, int xr, int yd,
+                                         int yu, float (&f)[72]) {
+    const char *base = (const char *)fin;
+    const unsigned pb4 = (unsigned)plane * 4u;
+    const rsrc_t rs = make_rsrc(base + 144LL * plane, 9u * pb4);
+    const unsigned cc = y * nx + x, cl = y * nx + xl, cr = y * nx + xr;
+    const unsigned dc = yd * nx + x, dl = yd * nx + xl, dr = yd * nx + xr;
+    const unsigned uc = yu * nx + x, ul = yu * nx + xl, ur = yu * nx + xr;
+    const float wA = (float)(S3H * 0.5), wB = (float)((1.0 - S3H) * 0.5);
+    SideRef C, A, B, D;
+    load_side(rs, cc, pb4, C);
+    // quadrant towards -x, -y: directions 0, 3 (axis), 1, 2
+    load_side(rs, cl, pb4, A);
+    load_side(rs, dc, pb4, B);
+    load_side(rs, dl, pb4, D);
+    dev_direction<ST, 0, 1>(base, plane, {cl}, {1.0f}, {&A}, f);
+    dev_direction<ST, 3, 1>(base, plane, {dc}, {1.0f}, {&B}, f);
+    dev_direction<ST, 1, 4>(base, plane, {dl, cl, dc, cc}, {wA, wA, wB, wB}, {&D, &A, &B, &C}, f);
+    dev_direction<ST, 2, 4>(base, plane, {dl, dc, cl, cc}, {wA, wA, wB, wB}, {&D, &B, &A, &C}, f);
+    // quadrant towards +x, -y: directions 6 (axis), 4, 5 (reuse the -y cell)
+    load_side(rs, cr, pb4, A);
+    load_side(rs, dr, pb4, D);
+    dev_direction<ST, 6, 1>(base, plane, {cr}, {1.0f}, {&A}, f);
+    dev_direction<ST, 4, 4>(base, plane, {dr, dc, cr, cc}, {wA, wA, wB, wB}, {&D, &B, &A, &C}, f);
+    dev_direction<ST, 5, 4>(base, plane, {dr, cr, dc, cc}, {wA, wA, wB, wB}, {&D, &A, &B, &C}, f);
+    // quadrant towards +x, +y: directions 9 (axis), 7, 8 (reuse the +x cell)
+    load_side(rs, uc, pb4, B);
+    load_side(rs, ur, pb4, D);
+    dev_direction<ST, 9, 1>(base, plane, {uc}, {1.0f}, {&B}, f);
+    dev_direction<ST, 7, 4>(base, plane, {ur, cr, uc, cc}, {wA, wA, wB, wB}, {&D, &A, &B, &C}, f);
+    dev_direction<ST, 8, 4>(base, plane, {ur, uc, cr, cc}, {wA, wA, wB, wB}, {&D, &B, &A, &C}, f);
+    // quadrant towards -x, +y: directions 10, 11 (reuse the +y cell)
+    load_side(rs, cl, pb4, A);
+    load_side(rs, ul, pb4, D);
+    dev_direction<ST, 10, 4>(base, plane, {ul, uc, cl, cc}, {wA, wA, wB, wB}, {&D, &B, &A, &C}, f);
+    dev_direction<ST, 11, 4>(base, plane, {ul, cl, uc, cc}, {wA, wA, wB, wB}, {&D, &A, &B, &C}, f);
+}
+
+template <int ST>
+__device__ __forceinline__ void store_dev(void *fout, long long plane, int off, const float (&f)[72]) {
+    char *base = (char *)fout;
+    const unsigned pb2 = (unsigned)plane * 2u, pb4 = (unsigned)plane * 4u;
+    float g[72];
+#pragma unroll
+    for (int q = 0; q < 72; ++q) g[q] = f[q] * (float)(1.0 / W_SHELL[ST][q % 6]);
+    float rho[6], A = 0.0f, B = 0.0f;
+    double pp = 0.0;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        float sum = 0.0f, sc = 0.0f, ss = 0.0f;
+#pragma unroll
+        for (int n = 0; n < 12; ++n) {
+            sum += g[6 * n + k];
+            sc += g[6 * n + k] * (float)cdir(n);
+            ss += g[6 * n + k] * (float)sdir(n);
+        }
+        rho[k] = sum * (1.0f / 12.0f);
+        A += (float)P_SHELL[ST][k] * sc;
+        B += (float)P_SHELL[ST][k] * ss;
+        pp += P_SHELL[ST][k] * P_SHELL[ST][k];
+    }
+    // least-squares dipole: sum_n cos^2 = 6 over the 12 directions
+    const float inv_den = (float)(1.0 / (6.0 * pp));
+    const float alpha = A * inv_den, beta = B * inv_den;
+    float smax = 0.0f;
+#pragma unroll
+    for (int n = 0; n < 12; ++n) {
+        const float tn = alpha * (float)cdir(n) + beta * (float)sdir(n);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            g[6 * n + k] -= rho[k] + (float)P_SHELL[ST][k] * tn;
+            smax = fmaxf(smax, fabsf(g[6 * n + k]));
+        }
+    }
+    const float inv = smax > 0.0f ? 1.0f / smax : 0.0f;
+#pragma unroll
+    for (int n = 0; n < 12; ++n) {
+        const rsrc_t r = make_rsrc(base + (long long)(6 * n) * plane * 2, 6u * pb2);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const _Float16 h = (_Float16)(g[6 * n + k] * inv);
+            __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, h), r, (unsigned)off * 2u,
+                                                  (unsigned)k * pb2, 0);
+        }
+    }
+    const rsrc_t rs = make_rsrc(base + 144LL * plane, 9u * pb4);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) bstore<float>(rho[k], rs, (unsigned)off * 4u, (unsigned)k * pb4);
+    bstore<float>(alpha, rs, (unsigned)off * 4u, 6u * pb4);
+    bstore<float>(beta, rs, (unsigned)off * 4u, 7u * pb4);
+    bstore<float>(smax, rs, (unsigned)off * 4u, 8u * pb4);
+}
+
 __device__ __forceinline__ void report(unsigned *status, unsigned flags) {
     if (flags) atomicOr(status, flags);
 }
@@ -597,7 +748,8 @@ __device__ __forceinline__ void step_cell(const KArgs &a, int x, int y) {
     int xl, xr, yd, yu;
     neighbours(a, xe, y, xl, xr, yd, yu);
     R f[72];
-    pull<S, R>((const S *)a.fin, a.plane, a.nx, xe, y, xl, xr, yd, yu, f);
+    if constexpr (std::is_same<S, Dev16>::value) pull_dev<ST>(a.fin, a.plane, a.nx, xe, y, xl, xr, yd, yu, f);
+    else pull<S, R>((const S *)a.fin, a.plane, a.nx, xe, y, xl, xr, yd, yu, f);
     const Mom m = moments<ST, R>(f);
     Macro M;
     int iters;
@@ -621,12 +773,13 @@ __device__ __forceinline__ void step_cell(const KArgs &a, int x, int y) {
         const double tau = (a.tau_mode == RLBM_TAU_CONST) ? a.tau : a.tau_a / M.theta + a.tau_b;
         equilibrium_relax<ST, true, R>(M, tau, f);
     }
-    store<S, R>((S *)a.fout, a.plane, y * a.nx + x, f);
+    if constexpr (std::is_same<S, Dev16>::value) store_dev<ST>(a.fout, a.plane, y * a.nx + x, f);
+    else store<S, R>((S *)a.fout, a.plane, y * a.nx + x, f);
     report(a.status, flags);
 }
 
 template <int ST, typename S, typename R>
-__global__ RLBM_STEP_BOUNDS(R) void k_step(KArgs a) {
+__global__ RLBM_STEP_BOUNDS(ST, R) void k_step(KArgs a) {
     int x, y;
     if (!cell_of(a, x, y)) return;
     step_cell<ST, S, R>(a, x, y);
@@ -644,7 +797,7 @@ struct Batch {
 };
 
 template <int ST, typename S, typename R>
-__global__ RLBM_STEP_BOUNDS(R) void k_step_batch(Batch b, const KArgs *__restrict__ descs,
+__global__ RLBM_STEP_BOUNDS(ST, R) void k_step_batch(Batch b, const KArgs *__restrict__ descs,
                                                  const int *__restrict__ tile_grid, const int *__restrict__ tile_base) {
     const int xcd = blockIdx.x & 7;
     const int lane_group = blockIdx.x >> 3;
@@ -672,7 +825,8 @@ __global__ __launch_bounds__(256) void k_moments(KArgs a) {
     int xl, xr, yd, yu;
     neighbours(a, x, y, xl, xr, yd, yu);
     R f[72];
-    pull<S, R>((const S *)a.fin, a.plane, a.nx, x, y, xl, xr, yd, yu, f);
+    if constexpr (std::is_same<S, Dev16>::value) pull_dev<ST>(a.fin, a.plane, a.nx, x, y, xl, xr, yd, yu, f);
+    else pull<S, R>((const S *)a.fin, a.plane, a.nx, x, y, xl, xr, yd, yu, f);
     const Mom m = moments<ST, R>(f);
     Macro M;
     int iters;
@@ -713,7 +867,8 @@ __global__ __launch_bounds__(256) void k_init(KArgs a) {
     else state_from_n_theta<ST>(a.i_n[off], th, M, flags);
     R f[72];
     equilibrium_relax<ST, false, R>(M, 1.0, f);
-    store<S, R>((S *)a.fout, a.plane, off, f);
+    if constexpr (std::is_same<S, Dev16>::value) store_dev<ST>(a.fout, a.plane, off, f);
+    else store<S, R>((S *)a.fout, a.plane, off, f);
     report(a.status, flags);
 }
 
@@ -724,12 +879,22 @@ using BFn = void (*)(Batch, const KArgs *, const int *, const int *);
 
 template <int ST>
 struct Kern {
-    static KFn step(int prec) { return prec == RLBM_FP64 ? k_step<ST, double, double> : k_step<ST, float, float>; }
-    static BFn batch(int prec) {
-        return prec == RLBM_FP64 ? k_step_batch<ST, double, double> : k_step_batch<ST, float, float>;
+    static KFn step(int prec) {
+        return prec == RLBM_FP64 ? k_step<ST, double, double>
+             : prec == RLBM_FP32 ? k_step<ST, float, float> : k_step<ST, Dev16, float>;
     }
-    static KFn mom(int prec) { return prec == RLBM_FP64 ? k_moments<ST, double, double> : k_moments<ST, float, float>; }
-    static KFn init(int prec) { return prec == RLBM_FP64 ? k_init<ST, double, double> : k_init<ST, float, float>; }
+    static BFn batch(int prec) {
+        return prec == RLBM_FP64 ? k_step_batch<ST, double, double>
+             : prec == RLBM_FP32 ? k_step_batch<ST, float, float> : k_step_batch<ST, Dev16, float>;
+    }
+    static KFn mom(int prec) {
+        return prec == RLBM_FP64 ? k_moments<ST, double, double>
+             : prec == RLBM_FP32 ? k_moments<ST, float, float> : k_moments<ST, Dev16, float>;
+    }
+    static KFn init(int prec) {
+        return prec == RLBM_FP64 ? k_init<ST, double, double>
+             : prec == RLBM_FP32 ? k_init<ST, float, float> : k_init<ST, Dev16, float>;
+    }
 };
 
 BFn pick_batch(int st, int prec) {
@@ -776,12 +941,13 @@ int validate(const rlbm_params *p) {
     if (!p) return RLBM_EINVAL;
     if (p->nx < 2 || p->ny < 2) return RLBM_EINVAL;
     {
-        const long long elem = p->precision == RLBM_FP64 ? 8 : 4;
-        if (6LL * p->nx * p->ny * elem > 0xFFFFFFFFLL) return RLBM_EINVAL;   // one buffer descriptor per direction
+        const long long elem = p->precision == RLBM_FP64 ? 8 : 4;   // F16DEV: its float side planes
+        const long long span = p->precision == RLBM_F16DEV ? 9 : 6;   // planes under one buffer descriptor
+        if (span * p->nx * p->ny * elem > 0xFFFFFFFFLL) return RLBM_EINVAL;
     }
     if (p->stats < RLBM_MJ || p->stats > RLBM_BE) return RLBM_EINVAL;
     if (p->order != 5) return (p->order >= 2 && p->order <= 4) ? RLBM_ENOTIMPL : RLBM_EINVAL;
-    if (p->precision != RLBM_FP64 && p->precision != RLBM_FP32) return RLBM_EINVAL;
+    if (p->precision != RLBM_FP64 && p->precision != RLBM_FP32 && p->precision != RLBM_F16DEV) return RLBM_EINVAL;
     if (p->tau_mode == RLBM_TAU_CONST) {
         if (!(p->tau > 0.0)) return RLBM_EINVAL;
     } else if (p->tau_mode == RLBM_TAU_INV_THETA) {

@@ -14,11 +14,12 @@ LIB_PATH = os.path.join(HERE, "librlbm.so")
 
 RLBM_OK, RLBM_EINVAL, RLBM_EDOMAIN, RLBM_EHIP, RLBM_ENONFINITE, RLBM_ENOTIMPL = 0, -1, -2, -3, -4, -5
 STATS = {"MJ": 0, "FD": 1, "BE": 2}
-PRECISION = {"fp64": 0, "fp32": 1}
+PRECISION = {"fp64": 0, "fp32": 1, "f16dev": 2}
 TAU_MODE = {"const": 0, "theta": 1}
 BC = {"periodic": 0, "open": 1, "wall": 2}
 GUESS = {"fixed": 0, "mlp": 1}
 DTYPE = {"fp64": torch.float64, "fp32": torch.float32}
+F16DEV_BYTES_PER_CELL = 180   # 72 half deviations + 9 float side values
 FIELD_NAMES = ("n", "eps", "theta", "z", "ux", "uy", "qx", "qy")
 
 FLAG_NONPOSITIVE, FLAG_SUPERLUMINAL, FLAG_CONDENSED, FLAG_RANGE, FLAG_NOCONV = 0x1, 0x2, 0x4, 0x8, 0x10
@@ -107,7 +108,10 @@ def _grid_args(params, init, device, stream):
     """Population buffers, rlbm_params and rlbm_init_fields for one grid."""
     nx, ny = int(params["nx"]), int(params["ny"])
     prec = params.get("precision", "fp64")
-    f = [torch.empty((72, ny, nx), dtype=DTYPE[prec], device=device) for _ in range(2)]
+    if prec == "f16dev":
+        f = [torch.empty(F16DEV_BYTES_PER_CELL * nx * ny // 4, dtype=torch.float32, device=device) for _ in range(2)]
+    else:
+        f = [torch.empty((72, ny, nx), dtype=DTYPE[prec], device=device) for _ in range(2)]
     bc = params.get("bc", ("periodic",) * 4)
     tw = params.get("theta_wall", (1.0, 1.0))
     p = Params(nx=nx, ny=ny, stats=STATS[params.get("stats", "MJ")], order=int(params.get("order", 5)),
@@ -202,6 +206,15 @@ class Sim:
             self.close()
         except Exception:
             pass
+
+
+def f16dev_views(buf, nx, ny):
+    """(deviation planes (72, ny, nx) float16, side planes (9, ny, nx) float32) of an
+    RLBM_F16DEV buffer (views, no copy)."""
+    raw = buf.view(torch.uint8)
+    dev = raw[: 144 * nx * ny].view(torch.float16).view(72, ny, nx)
+    side = raw[144 * nx * ny: 180 * nx * ny].view(torch.float32).view(9, ny, nx)
+    return dev, side
 
 
 class GuessNet:
