@@ -84,7 +84,8 @@ enum rlbm_guess { RLBM_GUESS_FIXED = 0, RLBM_GUESS_MLP = 1 };       /* FD/BE inv
 typedef struct rlbm_params {
     int32_t nx, ny;          /* grid size, both >= 2 (walls need nx >= 4) */
     int32_t stats;           /* rlbm_stats */
-    int32_t order;           /* expansion order; this build supports 5 */
+    int32_t order;           /* expansion order N of Eq. expansion-eq: 5 for every statistic; 2, 3, 4
+                                for Maxwell-Juttner with FP64/FP32 populations on single grids */
     int32_t precision;       /* rlbm_precision: element type of f_a, f_b */
     int32_t tau_mode;        /* rlbm_tau_mode */
     double tau;              /* constant relaxation time (> 0.5 recommended) */

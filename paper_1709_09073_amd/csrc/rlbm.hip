@@ -490,8 +490,16 @@ __device__ __forceinline__ void state_from_z_theta(double z, double theta, Macro
 // f^eq_{s,n} = sum_j r_j(s) A_{j,n};  r_j(s) = sum_k E^(j)_{s,k} G_k P_kj(u^2) (FP64),
 // A_{j,n} = Re[(u_x + i u_y)^j e^{-i j phi_n}], G_k = k! g_{k+1} theta^{k+1} gamma^k.
 // If COLLIDE: f <- f + omega_n (f^eq - f), omega_n = gamma (1 - v_n.u) / tau; else f <- f^eq.
-template <int ST, bool COLLIDE, typename R>
+// Projector table of expansion order N (5 for every statistic; 2..4 for Maxwell-Juttner).
+template <int ST, int N>
+__device__ __forceinline__ constexpr double emat(int pair, int shell) {
+    if constexpr (N == 5) return EMAT[ST][pair][shell];
+    else return EMAT_LO[N - 2][pair][shell];
+}
+
+template <int ST, bool COLLIDE, typename R, int N = 5>
 __device__ __forceinline__ void equilibrium_relax(const Macro &M, double tau, R (&f)[72]) {
+    static_assert(N == 5 || (ST == RLBM_MJ && N >= 2 && N <= 4), "lower orders are tabulated for MJ");
     const double u2 = M.ux * M.ux + M.uy * M.uy;
     double G[6];
     {
@@ -506,9 +514,9 @@ __device__ __forceinline__ void equilibrium_relax(const Macro &M, double tau, R 
     }
     double h[21];
 #pragma unroll
-    for (int j = 0; j < 6; ++j)
+    for (int j = 0; j <= N; ++j)
 #pragma unroll
-        for (int k = j; k < 6; ++k) {
+        for (int k = j; k <= N; ++k) {
             const int pi = pair_index(j, k);
             h[pi] = G[k] * (PKJ[pi][0] + u2 * (PKJ[pi][1] + u2 * PKJ[pi][2]));
         }
@@ -550,8 +558,10 @@ __device__ __forceinline__ void equilibrium_relax(const Macro &M, double tau, R 
 #pragma unroll
         for (int j = 0; j < 6; ++j) {
             double acc = 0.0;
+            if (j <= N) {
 #pragma unroll
-            for (int k = j; k < 6; ++k) acc += EMAT[ST][pair_index(j, k)][s] * h[pair_index(j, k)];
+                for (int k = j; k <= N; ++k) acc += emat<ST, N>(pair_index(j, k), s) * h[pair_index(j, k)];
+            }
             r[j] = (R)acc;
         }
 #pragma unroll
@@ -739,7 +749,7 @@ __device__ __forceinline__ void report(unsigned *status, unsigned flags) {
 
 // ---------------------------------------------------------------- kernels
 // One fused update of cell (x, y) of the grid described by a.
-template <int ST, typename S, typename R>
+template <int ST, typename S, typename R, int N = 5>
 __device__ __forceinline__ void step_cell(const KArgs &a, int x, int y) {
     unsigned flags = 0;
     const bool wall_lo = (a.bc_xlo == RLBM_BC_WALL_T) && x == 0;
@@ -768,21 +778,21 @@ __device__ __forceinline__ void step_cell(const KArgs &a, int x, int y) {
         // zeroth-order extrapolation of n and u, fixed wall temperature
         const double n = M.n;
         state_from_n_theta<ST>(n, wall_lo ? a.th_wall_lo : a.th_wall_hi, M, flags);
-        equilibrium_relax<ST, false, R>(M, 1.0, f);
+        equilibrium_relax<ST, false, R, N>(M, 1.0, f);
     } else {
         const double tau = (a.tau_mode == RLBM_TAU_CONST) ? a.tau : a.tau_a / M.theta + a.tau_b;
-        equilibrium_relax<ST, true, R>(M, tau, f);
+        equilibrium_relax<ST, true, R, N>(M, tau, f);
     }
     if constexpr (std::is_same<S, Dev16>::value) store_dev<ST>(a.fout, a.plane, y * a.nx + x, f);
     else store<S, R>((S *)a.fout, a.plane, y * a.nx + x, f);
     report(a.status, flags);
 }
 
-template <int ST, typename S, typename R>
+template <int ST, typename S, typename R, int N = 5>
 __global__ RLBM_STEP_BOUNDS(ST, R) void k_step(KArgs a) {
     int x, y;
     if (!cell_of(a, x, y)) return;
-    step_cell<ST, S, R>(a, x, y);
+    step_cell<ST, S, R, N>(a, x, y);
 }
 
 // Many grids in one launch.  The tiles of all grids are numbered consecutively
@@ -847,7 +857,7 @@ __global__ __launch_bounds__(256) void k_moments(KArgs a) {
     report(a.status, flags);
 }
 
-template <int ST, typename S, typename R>
+template <int ST, typename S, typename R, int N = 5>
 __global__ __launch_bounds__(256) void k_init(KArgs a) {
     int x, y;
     if (!cell_of(a, x, y)) return;
@@ -866,7 +876,7 @@ __global__ __launch_bounds__(256) void k_init(KArgs a) {
     if (a.given_z) state_from_z_theta<ST>(a.i_z[off], th, M, flags);
     else state_from_n_theta<ST>(a.i_n[off], th, M, flags);
     R f[72];
-    equilibrium_relax<ST, false, R>(M, 1.0, f);
+    equilibrium_relax<ST, false, R, N>(M, 1.0, f);
     if constexpr (std::is_same<S, Dev16>::value) store_dev<ST>(a.fout, a.plane, off, f);
     else store<S, R>((S *)a.fout, a.plane, off, f);
     report(a.status, flags);
@@ -896,6 +906,22 @@ struct Kern {
              : prec == RLBM_FP32 ? k_init<ST, float, float> : k_init<ST, Dev16, float>;
     }
 };
+
+// Maxwell-Juttner kernels of expansion order 2..4 (step, init), FP64 and FP32 storage
+template <int N>
+KFn pick_lo(int which, int prec) {
+    if (which == 0) return prec == RLBM_FP64 ? k_step<RLBM_MJ, double, double, N> : k_step<RLBM_MJ, float, float, N>;
+    return prec == RLBM_FP64 ? k_init<RLBM_MJ, double, double, N> : k_init<RLBM_MJ, float, float, N>;
+}
+
+KFn pick(int which, int st, int prec);
+
+KFn pick_order(int which, int st, int prec, int order) {
+    if (order == 5 || which == 1) return pick(which, st, prec);
+    if (order == 2) return pick_lo<2>(which, prec);
+    if (order == 3) return pick_lo<3>(which, prec);
+    return pick_lo<4>(which, prec);
+}
 
 BFn pick_batch(int st, int prec) {
     return st == RLBM_MJ ? Kern<RLBM_MJ>::batch(prec) : st == RLBM_FD ? Kern<RLBM_FD>::batch(prec) : Kern<RLBM_BE>::batch(prec);
@@ -946,7 +972,9 @@ int validate(const rlbm_params *p) {
         if (span * p->nx * p->ny * elem > 0xFFFFFFFFLL) return RLBM_EINVAL;
     }
     if (p->stats < RLBM_MJ || p->stats > RLBM_BE) return RLBM_EINVAL;
-    if (p->order != 5) return (p->order >= 2 && p->order <= 4) ? RLBM_ENOTIMPL : RLBM_EINVAL;
+    if (p->order < 2 || p->order > 5) return RLBM_EINVAL;
+    if (p->order != 5 && (p->stats != RLBM_MJ || p->precision == RLBM_F16DEV))
+        return RLBM_ENOTIMPL;   // lower orders: Maxwell-Juttner with FP64 or FP32 populations
     if (p->precision != RLBM_FP64 && p->precision != RLBM_FP32 && p->precision != RLBM_F16DEV) return RLBM_EINVAL;
     if (p->tau_mode == RLBM_TAU_CONST) {
         if (!(p->tau > 0.0)) return RLBM_EINVAL;
@@ -1090,7 +1118,7 @@ int launch_step(rlbm_ctx *c, hipStream_t s) {
         KArgs a = c->base[0];
         a.fin = c->cur ? p0.f_b : p0.f_a;
         a.fout = c->cur ? p0.f_a : p0.f_b;
-        hipLaunchKernelGGL(pick(0, p0.stats, p0.precision), dim3(8 * a.per_xcd), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(pick_order(0, p0.stats, p0.precision, p0.order), dim3(8 * a.per_xcd), dim3(256), 0, s, a);
     }
     c->cur ^= 1;
     c->steps++;
@@ -1131,7 +1159,8 @@ int finish_init(rlbm_ctx *c, const rlbm_init_fields *init) {
         ia.i_ux = init[g].ux;
         ia.i_uy = init[g].uy;
         ia.given_z = init[g].given_z;
-        hipLaunchKernelGGL(pick(2, p0.stats, p0.precision), dim3(8 * ia.per_xcd), dim3(256), 0, c->stream, ia);
+        hipLaunchKernelGGL(pick_order(2, p0.stats, p0.precision, p0.order), dim3(8 * ia.per_xcd), dim3(256), 0, c->stream,
+                           ia);
     }
     return hipGetLastError() == hipSuccess ? RLBM_OK : RLBM_EHIP;
 }
@@ -1145,6 +1174,7 @@ int create(rlbm_ctx **out, int ngrids, const rlbm_params *p, const rlbm_init_fie
         if (rc) return rc;
         if (!valid_init(&init[g])) return RLBM_EINVAL;
         const rlbm_params &a = p[g], &b = p[0];
+        if (ngrids > 1 && a.order != 5) return RLBM_ENOTIMPL;   // batches run the fifth-order kernels
         if (a.stats != b.stats || a.precision != b.precision || a.order != b.order || a.guess != b.guess ||
             a.mlp != b.mlp || a.stream != b.stream || a.tile_x != b.tile_x || a.tile_y != b.tile_y ||
             a.collect_stats != b.collect_stats)

@@ -116,13 +116,13 @@ def pkj_polynomials():
     return out
 
 
-def separable_projector(stats, nodes, lam):
-    """E^(j)_{s,k} for j = 0..5, k = j..5, s = 0..5 (mpmath)."""
+def separable_projector(stats, nodes, lam, order=5):
+    """E^(j)_{s,k} for j = 0..order, k = j..order, s = 0..5 (mpmath): projection onto V_order."""
     E = {}
     with mp.workdps(DPS):
-        for j in range(6):
+        for j in range(order + 1):
             cj = 2 * mp.pi if j == 0 else mp.pi
-            ks = list(range(j, 6))
+            ks = list(range(j, order + 1))
             G = mp.matrix(len(ks), len(ks))
             for a, k1 in enumerate(ks):
                 for b, k2 in enumerate(ks):
@@ -211,6 +211,15 @@ def emit(path):
     for E in E_all:
         body.append("{" + ", ".join("{" + ", ".join(_fmt(E[(j, k, s)]) for s in range(6)) + "}" for (j, k) in pairs) + "}")
     lines.append("constexpr double EMAT[3][21][6] = {%s};" % ", ".join(body))
+    # lower expansion orders (Maxwell-Juttner): same pair layout, zero where k > order
+    lines.append("// projector of order N = 2, 3, 4 for Maxwell-Juttner, EMAT_LO[N - 2][pair][shell]")
+    mj_nodes, mj_lam = golub_welsch(radial_moments("MJ"))
+    lo = []
+    for order in (2, 3, 4):
+        El = separable_projector("MJ", mj_nodes, mj_lam, order)
+        lo.append("{" + ", ".join("{" + ", ".join(_fmt(El.get((j, k, s_), 0)) for s_ in range(6)) + "}"
+                                  for (j, k) in pairs) + "}")
+    lines.append("constexpr double EMAT_LO[3][21][6] = {%s};" % ", ".join(lo))
     P = pkj_polynomials()
     lines.append("// P_kj(x) = c0 + c1 x + c2 x^2 including the factor 2 pi, per pair (j, k)")
     with mp.workdps(DPS):

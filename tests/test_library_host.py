@@ -51,7 +51,7 @@ def _params(**kw):
 
 
 INVALID = [
-    dict(nx=1), dict(ny=0), dict(stats=3), dict(order=7), dict(precision=5), dict(tau=0.0),
+    dict(nx=1), dict(ny=0), dict(stats=3), dict(order=7), dict(order=1), dict(precision=5), dict(tau=0.0),
     dict(tau_mode=1, tau_b=0.0), dict(tau_mode=2), dict(bc=[0, 1, 0, 0]), dict(bc=[0, 0, 2, 2]),
     dict(bc=[2, 2, 0, 0], nx=3), dict(f_a=ctypes.c_void_p(0)), dict(f_b=ctypes.c_void_p(0x1000)),
     dict(tile_x=48, tile_y=5), dict(tile_x=8, tile_y=32), dict(tile_x=64, tile_y=2),
@@ -69,9 +69,9 @@ def test_invalid_params_rejected(rl, kw):
     assert not ctx.value
 
 
-def test_lower_orders_not_in_this_build(rl):
+def test_lower_orders_only_for_maxwell_juttner(rl):
     L = rl.lib()
-    p = _params(order=3)
+    p = _params(order=3, stats=1)
     fi = rl.InitFields(n=ctypes.c_void_p(0x10), z=None, theta=ctypes.c_void_p(0x10), ux=ctypes.c_void_p(0x10),
                        uy=ctypes.c_void_p(0x10), given_z=0)
     ctx = ctypes.c_void_p()

@@ -12,6 +12,7 @@ Workloads (the paper uses formula-defined initial-value problems, no datasets):
 * fourier          - heat conduction between fixed-temperature walls (Sec. 3.3)
 * hotspot_fd       - Fermi-Dirac Gaussian hot spot with a seeded smooth fugacity
 * hotspot_be       - Bose-Einstein field of 16 seeded Gaussian bumps
+* hotspot_paper    - the paper's Maxwell-Juttner hot spot (Sec. 3.5)
 * smooth_random    - seeded smooth random fields for parity tests
 * batch_specs      - 64 uneven Taylor-Green and Fourier grids for sweeps
 """
@@ -108,6 +109,18 @@ def hotspot_be(L=8192, seed=5, nbumps=16, device="cpu"):
     fields = dict(z=torch.clamp(zz, 0.2, 0.9).contiguous(), theta=th.contiguous(),
                   ux=torch.zeros_like(x), uy=torch.zeros_like(x))
     params = dict(nx=L, ny=L, stats="BE", tau_mode="theta", tau_a=2.0, tau_b=0.2546, bc=("open",) * 4)
+    return params, fields
+
+
+def hotspot_paper(L=512, radius=32.0, theta_in=1.5, theta_out=0.5, device="cpu"):
+    """Hot spot of Sec. 3.5: theta_in inside (x - L/2)^2 + (y - L/2)^2 <= radius^2,
+    theta_out elsewhere, n = 1, u = 0, open boundaries, tau = 2/theta + 0.2546
+    (eta/s = 0.5)."""
+    x, y = _grid(L, L, device)
+    inside = (x - L / 2) ** 2 + (y - L / 2) ** 2 <= radius ** 2
+    th = torch.where(inside, torch.full_like(x, theta_in), torch.full_like(x, theta_out))
+    fields = dict(n=torch.ones_like(x), theta=th.contiguous(), ux=torch.zeros_like(x), uy=torch.zeros_like(x))
+    params = dict(nx=L, ny=L, stats="MJ", tau_mode="theta", tau_a=2.0, tau_b=0.2546, bc=("open",) * 4)
     return params, fields
 
 
