@@ -121,7 +121,7 @@ def cpu_baseline(name, budget_s=15.0):
                        f"in {dt:.1f} s")
 
 
-def train_guess_net(name, device):
+def train_guess_net(name, device, iters=3000):
     """Train the inversion-guess network on (ln r, ln z) pairs from a 512^2 run of the
     same workload family (100 steps), with the library's training kernels."""
     import numpy as np
@@ -141,11 +141,78 @@ def train_guess_net(name, device):
     net = rlbm.GuessNet()
     noise = torch.from_numpy(np.random.default_rng(0).standard_normal(rlbm.MLP_HIDDEN + 1).astype(np.float32)).to(device)
     net.init(x, t, noise)
-    losses = net.train(x, t, iters=3000, lr=3e-3)
+    print(f"[bench] training the inversion-guess network: {x.numel()} pairs, {iters} Adam steps",
+          file=sys.stderr, flush=True)
+    losses = net.train(x, t, iters=iters, lr=3e-3)
     torch.cuda.synchronize()
     err = (net.predict(x) - t.reshape(-1)).abs().max().item()
-    return net, dict(samples=int(x.numel()), iters=3000, loss_first=float(losses[0]), loss_last=float(losses[-1]),
+    return net, dict(samples=int(x.numel()), iters=iters, loss_first=float(losses[0]), loss_last=float(losses[-1]),
                      max_abs_err_ln_z=err)
+
+
+def time_steps(sim, steps, warmup):
+    import torch
+    sim.step(warmup)
+    sim.capture()          # graph capture and instantiation stay outside the timed region
+    sim.sync()
+    torch.cuda.synchronize()
+    stream = sim.stream
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    sim.step(steps)
+    e1.record(stream)
+    e1.synchronize()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def variants(name, net, steps):
+    """MLUPS of the other storage / inversion-start variants on the same workload."""
+    from paper_1709_09073_amd import rlbm
+    out = {}
+    for prec in ("fp32", "f16dev"):
+        for guess in ("fixed", "mlp"):
+            if guess == "mlp" and net is None:
+                continue
+            params, fields = build_workload(name, "cuda")
+            params.update(precision=prec)
+            if guess == "mlp":
+                params.update(guess="mlp", mlp=net.w)
+            sim = rlbm.Sim(params, fields)
+            ms = time_steps(sim, steps, 20)
+            sim.close()
+            out[f"{prec}_{guess}"] = round(params["nx"] * params["ny"] * steps / (ms * 1e-3) / 1e6, 1)
+    return out
+
+
+def error_vs_fp64(name, steps=400, L=256):
+    """eps_theta and eps_q (Sec. 3.5 norms) of FP32 and FP16-deviation storage against
+    the FP64 path after `steps` steps of a 256^2 version of the hot spot."""
+    import numpy as np
+    import workloads
+    from paper_1709_09073_amd import rlbm
+    if name.startswith("fd_hotspot"):
+        params, fields = workloads.hotspot_fd(L=L, seed=4, sigma=L / 32, device="cuda")
+    elif name.startswith("be_hotspot"):
+        params, fields = workloads.hotspot_be(L=L, seed=5, device="cuda")
+    else:
+        return None
+    res = {}
+    for prec in ("fp64", "fp32", "f16dev"):
+        sim = rlbm.Sim(dict(params, precision=prec), fields)
+        sim.step(steps)
+        res[prec] = {k: v.cpu().numpy() for k, v in sim.fields().items()}
+        sim.close()
+    ref = res["fp64"]
+    out = {"grid": [L, L], "steps": steps}
+    for prec in ("fp32", "f16dev"):
+        r = res[prec]
+        et = float(np.abs(r["theta"] - ref["theta"]).sum() / ref["theta"].sum())
+        eq = float((np.abs(r["qx"] - ref["qx"]).sum() + np.abs(r["qy"] - ref["qy"]).sum())
+                   / (np.abs(ref["qx"]).sum() + np.abs(ref["qy"]).sum()))
+        out[prec] = {"eps_theta": et, "eps_q": eq}
+    return out
 
 
 def main():
@@ -157,7 +224,9 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "f16dev"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile", default="auto", help="workgroup tile TXxTY (e.g. 64x4) or auto")
-    ap.add_argument("--guess", default="fixed", choices=["fixed", "mlp"],
+    ap.add_argument("--no-variants", action="store_true", help="skip the other storage/guess variants")
+    ap.add_argument("--guess-iters", type=int, default=3000, help="Adam steps when training the guess network")
+    ap.add_argument("--guess", default="mlp", choices=["fixed", "mlp"],
                     help="FD/BE inversion start: fixed, or the network trained on a smaller run first")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -177,7 +246,7 @@ def main():
           f"warmup={args.warmup} steps={args.steps}", file=sys.stderr, flush=True)
     net, net_info = (None, None)
     if args.guess == "mlp":
-        net, net_info = train_guess_net(args.workload, dev)
+        net, net_info = train_guess_net(args.workload, dev, args.guess_iters)
         if net is not None:
             params["guess"] = "mlp"
             params["mlp"] = net.w
@@ -197,19 +266,7 @@ def main():
         sim = rlbm.Sim(params, fields)
         ncell = params["nx"] * params["ny"]
     del fields
-    sim.step(args.warmup)
-    sim.capture()          # graph capture and instantiation stay outside the timed region
-    sim.sync()
-    torch.cuda.synchronize()
-    stream = sim.stream
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    sim.step(args.steps)
-    e1.record(stream)
-    e1.synchronize()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
+    ms = time_steps(sim, args.steps, args.warmup)
     status = sim.status()
     mlups = ncell * args.steps / (ms * 1e-3) / 1e6
     cell_bytes = {"fp64": 72 * 8, "fp32": 72 * 4, "f16dev": 180}[args.precision]
@@ -242,6 +299,10 @@ def main():
                      "traffic": recorded_traffic(args.workload, args.precision),
                      "algorithmic_bytes_per_launch": bytes_per_launch, "kernel": "k_step"},
     }
+    if not args.no_variants and args.workload in ("fd_hotspot_2048", "be_hotspot_8192"):
+        vsteps = max(100, min(args.steps, 500))
+        out["variants"] = {"unit": "MLUPS", "steps": vsteps, **variants(args.workload, net, vsteps)}
+        out["error_vs_fp64"] = error_vs_fp64(args.workload)
     if not args.no_cpu_baseline and args.workload != "batched_sweep_64":
         out["cpu_baseline"] = cpu_baseline(args.workload)
     print(json.dumps(out), flush=True)

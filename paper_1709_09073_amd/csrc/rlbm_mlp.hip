@@ -17,9 +17,11 @@ constexpr int BLOCK = 256;
 
 // Workspace layout (floats): per-sample gradient columns G[(NTRAIN + 1) x n] (the
 // last column holds the per-sample loss), the summed gradient and loss
-// (NTRAIN + 1), Adam's first and second moments (NTRAIN each), init statistics (4).
+// (NTRAIN + 1), Adam's first and second moments (NTRAIN each), init statistics (4),
+// then, 8-byte aligned, the first-stage column sums in double ((NTRAIN + 1) x PARTS).
 struct Workspace {
     float *G, *grad, *m, *v, *stats;
+    double *partial;   // (NTRAIN + 1) x PARTS first-stage sums
 };
 
 Workspace carve(void *ws, long long n) {
@@ -30,6 +32,10 @@ Workspace carve(void *ws, long long n) {
     w.m = w.grad + (NTRAIN + 1);
     w.v = w.m + NTRAIN;
     w.stats = w.v + NTRAIN;
+    // 8-byte aligned start for the partial sums
+    uintptr_t q = reinterpret_cast<uintptr_t>(w.stats + 4);
+    q = (q + 7) & ~uintptr_t(7);
+    w.partial = reinterpret_cast<double *>(q);
     return w;
 }
 
@@ -63,19 +69,37 @@ __global__ __launch_bounds__(BLOCK) void k_sample_grads(const float *__restrict_
     G[(long long)NTRAIN * n + i] = r * r * inv_n;          // loss share
 }
 
-// out[c] = sum_i G[c][i], one workgroup per column, fixed summation order.
-__global__ __launch_bounds__(BLOCK) void k_column_sums(const float *__restrict__ G, long long n, float *__restrict__ out) {
-    const float *col = G + (long long)blockIdx.x * n;
-    double acc = 0.0;
-    for (long long i = threadIdx.x; i < n; i += BLOCK) acc += (double)col[i];
+constexpr int PARTS = 64;   // workgroups per column in the first reduction stage
+
+__device__ __forceinline__ double block_sum(double v) {
     __shared__ double sm[BLOCK];
-    sm[threadIdx.x] = acc;
+    sm[threadIdx.x] = v;
     __syncthreads();
     for (int st = BLOCK / 2; st > 0; st >>= 1) {
         if ((int)threadIdx.x < st) sm[threadIdx.x] += sm[threadIdx.x + st];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[blockIdx.x] = (float)sm[0];
+    return sm[0];
+}
+
+// Stage 1: partial[c][p] = sum of G[c][i] over the p-th contiguous chunk of i
+// (grid: PARTS x columns).  Stage 2: out[c] = sum_p partial[c][p].  Both stages sum
+// in a fixed order, so the result does not depend on scheduling.
+__global__ __launch_bounds__(BLOCK) void k_column_partials(const float *__restrict__ G, long long n,
+                                                           double *__restrict__ partial) {
+    const int part = blockIdx.x, c = blockIdx.y;
+    const long long chunk = (n + PARTS - 1) / PARTS;
+    const long long lo = part * chunk, hi = lo + chunk < n ? lo + chunk : n;
+    const float *col = G + (long long)c * n;
+    double acc = 0.0;
+    for (long long i = lo + threadIdx.x; i < hi; i += BLOCK) acc += (double)col[i];
+    const double s = block_sum(acc);
+    if (threadIdx.x == 0) partial[(long long)c * PARTS + part] = s;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_column_final(const double *__restrict__ partial, float *__restrict__ out) {
+    const double s = block_sum(threadIdx.x < PARTS ? partial[(long long)blockIdx.x * PARTS + threadIdx.x] : 0.0);
+    if (threadIdx.x == 0) out[blockIdx.x] = (float)s;
 }
 
 __global__ void k_fill(float *p, int n, float v) {
@@ -155,7 +179,8 @@ unsigned blocks_for(long long n) { return (unsigned)((n + BLOCK - 1) / BLOCK); }
 int loss_grad_enqueue(const float *w, const float *x, const float *t, long long n, const Workspace &ws,
                       hipStream_t s) {
     hipLaunchKernelGGL(k_sample_grads, dim3(blocks_for(n)), dim3(BLOCK), 0, s, w, x, t, n, ws.G);
-    hipLaunchKernelGGL(k_column_sums, dim3(NTRAIN + 1), dim3(BLOCK), 0, s, ws.G, n, ws.grad);
+    hipLaunchKernelGGL(k_column_partials, dim3(PARTS, NTRAIN + 1), dim3(BLOCK), 0, s, ws.G, n, ws.partial);
+    hipLaunchKernelGGL(k_column_final, dim3(NTRAIN + 1), dim3(BLOCK), 0, s, ws.partial, ws.grad);
     return hipGetLastError() == hipSuccess ? RLBM_OK : RLBM_EHIP;
 }
 
@@ -165,7 +190,8 @@ extern "C" {
 
 uint64_t rlbm_mlp_workspace_bytes(int64_t n) {
     if (n < 1) return 0;
-    return sizeof(float) * ((uint64_t)(NTRAIN + 1) * (uint64_t)(n + 1) + 2u * NTRAIN + 4u);
+    return sizeof(float) * ((uint64_t)(NTRAIN + 1) * (uint64_t)(n + 1) + 2u * NTRAIN + 4u) + 8u +
+           sizeof(double) * (uint64_t)(NTRAIN + 1) * PARTS;
 }
 
 int rlbm_mlp_init(float *w, const float *x, const float *t, int64_t n, const float *noise, void *workspace,
