@@ -70,7 +70,8 @@ def build_workload(name, device):
 def kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
-    for rel in ("paper_1709_09073_amd/csrc/rlbm.hip", "paper_1709_09073_amd/csrc/rlbm_tables.h"):
+    for rel in ("paper_1709_09073_amd/csrc/rlbm.hip", "paper_1709_09073_amd/csrc/rlbm_tables.h",
+                "paper_1709_09073_amd/csrc/rlbm_mlp.h"):
         with open(os.path.join(ROOT, rel), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
