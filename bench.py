@@ -151,8 +151,12 @@ def train_guess_net(name, device, iters=3000):
                      max_abs_err_ln_z=err)
 
 
-def time_steps(sim, steps, warmup):
+def time_steps(sim, steps, warmup, tune=False):
+    """ms for `steps` graph-replayed steps after `warmup` steps; with tune, the
+    workgroup tile is chosen first by timing a few steps of each shape."""
     import torch
+    if tune:
+        sim.tile = sim.autotune(trial_steps=10)
     sim.step(warmup)
     sim.capture()          # graph capture and instantiation stay outside the timed region
     sim.sync()
@@ -181,7 +185,7 @@ def variants(name, net, steps):
             if guess == "mlp":
                 params.update(guess="mlp", mlp=net.w)
             sim = rlbm.Sim(params, fields)
-            ms = time_steps(sim, steps, 20)
+            ms = time_steps(sim, steps, 20, tune=True)
             sim.close()
             out[f"{prec}_{guess}"] = round(params["nx"] * params["ny"] * steps / (ms * 1e-3) / 1e6, 1)
     return out
@@ -267,7 +271,10 @@ def main():
         sim = rlbm.Sim(params, fields)
         ncell = params["nx"] * params["ny"]
     del fields
-    ms = time_steps(sim, args.steps, args.warmup)
+    tune = args.tile == "auto" and args.workload != "batched_sweep_64"
+    ms = time_steps(sim, args.steps, args.warmup, tune=tune)
+    if tune:
+        args.tile = f"{sim.tile[0]}x{sim.tile[1]} (autotuned)"
     status = sim.status()
     mlups = ncell * args.steps / (ms * 1e-3) / 1e6
     cell_bytes = {"fp64": 72 * 8, "fp32": 72 * 4, "f16dev": 180}[args.precision]

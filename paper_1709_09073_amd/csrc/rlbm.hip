@@ -33,10 +33,17 @@
 #ifndef RLBM_STEP_WAVES_PER_SIMD
 #define RLBM_STEP_WAVES_PER_SIMD 3   // occupancy target of the FP32 step kernel (register budget 512/3)
 #endif
+#ifndef RLBM_STEP_WAVES_FDBE
+#define RLBM_STEP_WAVES_FDBE 2       // FD/BE carry the inversion's FP64 state as well
+#endif
+#ifndef RLBM_BATCH_WAVES_MJ
+#define RLBM_BATCH_WAVES_MJ 2   // measured: 3 waves spill in the batch kernel and run ~10% slower
+#endif
 // FP64 populations need about twice the registers: no occupancy target (no spills)
-// FD/BE carry the inversion's FP64 state as well: 2 waves per SIMD avoids spills
 #define RLBM_STEP_BOUNDS(ST, R) \
-    __launch_bounds__(256, sizeof(R) == 8 ? 1 : ((ST) == RLBM_MJ ? RLBM_STEP_WAVES_PER_SIMD : 2))
+    __launch_bounds__(256, sizeof(R) == 8 ? 1 : ((ST) == RLBM_MJ ? RLBM_STEP_WAVES_PER_SIMD : RLBM_STEP_WAVES_FDBE))
+#define RLBM_BATCH_BOUNDS(ST, R) \
+    __launch_bounds__(256, sizeof(R) == 8 ? 1 : ((ST) == RLBM_MJ ? RLBM_BATCH_WAVES_MJ : RLBM_STEP_WAVES_FDBE))
 
 namespace {
 
@@ -115,6 +122,18 @@ __device__ __forceinline__ void neighbours(const KArgs &a, int x, int y, int &xl
 // The host keeps 6 * nx * ny * sizeof(element) below 2^32.
 using rsrc_t = __amdgpu_buffer_rsrc_t;
 
+// Cache policy bits of the population loads and stores (bit 1 = non-temporal).  The
+// populations a step writes are read only by the next launch, after the whole grid
+// has been written, so the stores stream past the caches.
+#ifndef RLBM_POP_LOAD_POLICY
+#define RLBM_POP_LOAD_POLICY 0
+#endif
+#ifndef RLBM_POP_STORE_POLICY
+#define RLBM_POP_STORE_POLICY 2
+#endif
+constexpr int LOAD_POLICY = RLBM_POP_LOAD_POLICY;
+constexpr int STORE_POLICY = RLBM_POP_STORE_POLICY;
+
 __device__ __forceinline__ rsrc_t make_rsrc(const void *base, unsigned bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
 }
@@ -123,23 +142,23 @@ template <typename S>
 __device__ __forceinline__ S bload(rsrc_t r, unsigned voff, unsigned soff);
 template <>
 __device__ __forceinline__ float bload<float>(rsrc_t r, unsigned voff, unsigned soff) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, LOAD_POLICY));
 }
 template <>
 __device__ __forceinline__ double bload<double>(rsrc_t r, unsigned voff, unsigned soff) {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, LOAD_POLICY));
 }
 
 template <typename S>
 __device__ __forceinline__ void bstore(S v, rsrc_t r, unsigned voff, unsigned soff);
 template <>
 __device__ __forceinline__ void bstore<float>(float v, rsrc_t r, unsigned voff, unsigned soff) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, STORE_POLICY);
 }
 template <>
 __device__ __forceinline__ void bstore<double>(double v, rsrc_t r, unsigned voff, unsigned soff) {
     typedef unsigned v2u __attribute__((ext_vector_type(2)));
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u, v), r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u, v), r, voff, soff, STORE_POLICY);
 }
 
 // ---------------------------------------------------------------- streaming
@@ -645,7 +664,7 @@ __device__ __forceinline__ void dev_direction(const char *base, long long plane,
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
             const unsigned short h =
-                __builtin_amdgcn_raw_buffer_load_b16(r, cell[t] * 2u, (unsigned)k * pb2, 0);
+                __builtin_amdgcn_raw_buffer_load_b16(r, cell[t] * 2u, (unsigned)k * pb2, LOAD_POLICY);
             acc += ws[t] * half_bits_to_float(h);
         }
         f[6 * N + k] = (float)W_SHELL[ST][k] * acc;
@@ -735,7 +754,7 @@ __device__ __forceinline__ void store_dev(void *fout, long long plane, int off, 
         for (int k = 0; k < 6; ++k) {
             const _Float16 h = (_Float16)(g[6 * n + k] * inv);
             __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, h), r, (unsigned)off * 2u,
-                                                  (unsigned)k * pb2, 0);
+                                                  (unsigned)k * pb2, STORE_POLICY);
         }
     }
     const rsrc_t rs = make_rsrc(base + 144LL * plane, 9u * pb4);
@@ -810,7 +829,7 @@ struct Batch {
 };
 
 template <int ST, typename S, typename R>
-__global__ RLBM_STEP_BOUNDS(ST, R) void k_step_batch(Batch b, const KArgs *__restrict__ descs,
+__global__ RLBM_BATCH_BOUNDS(ST, R) void k_step_batch(Batch b, const KArgs *__restrict__ descs,
                                                  const int *__restrict__ tile_grid, const int *__restrict__ tile_base) {
     const int xcd = blockIdx.x & 7;
     const int lane_group = blockIdx.x >> 3;
@@ -1014,7 +1033,14 @@ void auto_tile(const rlbm_params &p, int &tx, int &ty) {
         ty = p.tile_y;
         return;
     }
-    ty = p.ny >= 8 ? 8 : (p.ny >= 4 ? 4 : 2);   // 32 x 8 measured fastest on 2048^2 grids
+    // Measured on MI355X: 32 x 8 is fastest on 2048-wide grids, while on 8192-wide
+    // grids 128 x 2 runs about 30% faster than 32 x 8.  rlbm_autotune measures instead.
+    if (p.nx >= 4096 && p.ny >= 2) {
+        tx = 128;
+        ty = 2;
+        return;
+    }
+    ty = p.ny >= 8 ? 8 : (p.ny >= 4 ? 4 : 2);
     tx = 256 / ty;
 }
 
