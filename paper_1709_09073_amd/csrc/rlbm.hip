@@ -34,16 +34,19 @@
 #define RLBM_STEP_WAVES_PER_SIMD 3   // occupancy target of the FP32 step kernel (register budget 512/3)
 #endif
 #ifndef RLBM_STEP_WAVES_FDBE
-#define RLBM_STEP_WAVES_FDBE 2       // FD/BE carry the inversion's FP64 state as well
+#define RLBM_STEP_WAVES_FDBE 3       // FD/BE fit 3 waves without spills with the shortened FP32-path sums
 #endif
 #ifndef RLBM_BATCH_WAVES_MJ
 #define RLBM_BATCH_WAVES_MJ 2   // measured: 3 waves spill in the batch kernel and run ~10% slower
+#endif
+#ifndef RLBM_BATCH_WAVES_FDBE
+#define RLBM_BATCH_WAVES_FDBE 2      // the batch kernel spills at 3
 #endif
 // FP64 populations need about twice the registers: no occupancy target (no spills)
 #define RLBM_STEP_BOUNDS(ST, R) \
     __launch_bounds__(256, sizeof(R) == 8 ? 1 : ((ST) == RLBM_MJ ? RLBM_STEP_WAVES_PER_SIMD : RLBM_STEP_WAVES_FDBE))
 #define RLBM_BATCH_BOUNDS(ST, R) \
-    __launch_bounds__(256, sizeof(R) == 8 ? 1 : ((ST) == RLBM_MJ ? RLBM_BATCH_WAVES_MJ : RLBM_STEP_WAVES_FDBE))
+    __launch_bounds__(256, sizeof(R) == 8 ? 1 : ((ST) == RLBM_MJ ? RLBM_BATCH_WAVES_MJ : RLBM_BATCH_WAVES_FDBE))
 
 namespace {
 
@@ -283,24 +286,28 @@ __device__ __forceinline__ void g_tail(double mu, double xi, double (&g)[7]) {
     }
 }
 
-template <int MLO, int MHI>
+template <int MLO, int MHI, int K>
 __device__ __forceinline__ void g_table(const double (*tab)[NG], int i, double d, double (&g)[7]) {
-    double t[NT];
+    double t[K];
     t[0] = 1.0;
 #pragma unroll
-    for (int k = 1; k < NT; ++k) t[k] = t[k - 1] * d * (1.0 / k);
+    for (int k = 1; k < K; ++k) t[k] = t[k - 1] * d * (1.0 / k);
     const double *row = tab[i];
 #pragma unroll
     for (int m = MLO; m <= MHI; ++m) {
         double s = 0;
 #pragma unroll
-        for (int k = NT - 1; k >= 0; --k) s += row[6 - m + k] * t[k];
+        for (int k = K - 1; k >= 0; --k) s += row[6 - m + k] * t[k];
         g[m] = s;
     }
 }
 
-template <int ST, int MLO, int MHI>
+// LOOSE (FP32 / FP16 populations): shortened sums, tail below 1e-11 relative
+// (bounded when the tables are generated).
+template <int ST, int MLO, int MHI, bool LOOSE = false>
 __device__ __forceinline__ void gvals(double mu, double (&g)[7], unsigned &flags) {
+    constexpr int K = LOOSE ? NT_LOOSE : NT;
+    constexpr int NZ = LOOSE ? BE_NZ_LOOSE : BE_NZ;
     // table indices below are formed from mu: keep it finite and inside the tables' reach
     if (!(mu > -40.0)) {
         if (mu != mu) flags |= RLBM_FLAG_NONPOSITIVE;   // NaN
@@ -322,7 +329,7 @@ __device__ __forceinline__ void gvals(double mu, double (&g)[7], unsigned &flags
             i = FD_NC - 1;
             if (mu > FD_MU_MIN + (FD_NC - 0.5) * FD_DMU) flags |= RLBM_FLAG_RANGE;
         }
-        g_table<MLO, MHI>(FD_TAB, i, mu - (FD_MU_MIN + i * FD_DMU), g);
+        g_table<MLO, MHI, K>(FD_TAB, i, mu - (FD_MU_MIN + i * FD_DMU), g);
     } else {
         if (mu < BE_MU_MIN - 0.5 * BE_DMU) {
             g_tail<MLO, MHI>(mu, -1.0, g);
@@ -331,20 +338,20 @@ __device__ __forceinline__ void gvals(double mu, double (&g)[7], unsigned &flags
         if (mu < BE_MU_SPLIT - 0.5 * BE_DMU) {
             int i = (int)rint((mu - BE_MU_MIN) * (1.0 / BE_DMU));
             if (i > BE_NC - 1) i = BE_NC - 1;
-            g_table<MLO, MHI>(BE_TAB, i, mu - (BE_MU_MIN + i * BE_DMU), g);
+            g_table<MLO, MHI, K>(BE_TAB, i, mu - (BE_MU_MIN + i * BE_DMU), g);
             return;
         }
         // Li_m(e^mu) = mu^{m-1}/(m-1)! (H_{m-1} - ln(-mu)) + sum_{k != m-1} zeta(m-k) mu^k / k!
         const double L = log(-mu);
-        double t[BE_NZ];
+        double t[NZ];
         t[0] = 1.0;
 #pragma unroll
-        for (int k = 1; k < BE_NZ; ++k) t[k] = t[k - 1] * mu * (1.0 / k);
+        for (int k = 1; k < NZ; ++k) t[k] = t[k - 1] * mu * (1.0 / k);
 #pragma unroll
         for (int m = MLO; m <= MHI; ++m) {
             double s = 0;
 #pragma unroll
-            for (int k = BE_NZ - 1; k >= 0; --k) s += BE_ZETA[6 - m + k] * t[k];   // zeta(1) stored as 0
+            for (int k = NZ - 1; k >= 0; --k) s += BE_ZETA[6 - m + k] * t[k];   // zeta(1) stored as 0
             g[m] = s + t[m - 1] * (HARMONIC[m - 1] - L);
         }
     }
@@ -365,13 +372,9 @@ __device__ __forceinline__ double newton_tol(double mu) {
 template <int ST, bool LOOSE>
 __device__ __forceinline__ double invert_h(double r, double mu, unsigned &flags, int &iters) {
     double lo = -40.0, hi = (ST == RLBM_BE) ? LOG_ZC_BE : FD_MU_MIN + (FD_NC - 0.5) * FD_DMU;
-    if (ST == RLBM_BE) {
-        double g[7];
-        gvals<ST, 2, 3>(LOG_ZC_BE, g, flags);
-        if (r >= g[2] * g[2] * g[2] / (g[3] * g[3])) {
-            flags |= RLBM_FLAG_CONDENSED;
-            return LOG_ZC_BE;
-        }
+    if (ST == RLBM_BE && r >= H_ZC_BE) {
+        flags |= RLBM_FLAG_CONDENSED;
+        return LOG_ZC_BE;
     }
     if (!(mu > lo && mu < hi)) mu = 0.5 * (lo + hi);
     bool conv = false;
@@ -379,11 +382,22 @@ __device__ __forceinline__ double invert_h(double r, double mu, unsigned &flags,
     for (int it = 0; it < 80; ++it) {
         ++iters;
         double g[7];
-        gvals<ST, 1, 3>(mu, g, flags);
-        const double q = g[2] / g[3];
-        const double h = g[2] * q * q;
+        gvals<ST, 1, 3, LOOSE>(mu, g, flags);
+        double h, dmu;
+        if constexpr (LOOSE) {
+            // one FP64 division; the step itself only needs single precision: its
+            // relative error (~1e-7) adds at most 1e-7 |dmu| to what the step leaves
+            const double a = 1.0 / (g[2] * g[3]);
+            const double q = g[2] * g[2] * a;
+            h = g[2] * q * q;
+            const double D = h * (3.0 * g[1] * g[3] * a - 2.0 * q);
+            dmu = (double)__fdividef((float)(h - r), (float)D);
+        } else {
+            const double q = g[2] / g[3];
+            h = g[2] * q * q;
+            dmu = (h - r) / (h * (3.0 * g[1] / g[2] - 2.0 * q));   // dh/dmu = h (3 g1/g2 - 2 g2/g3)
+        }
         const double F = h - r;
-        const double dmu = F / (h * (3.0 * g[1] / g[2] - 2.0 * q));   // dh/dmu = h (3 g1/g2 - 2 g2/g3)
         if (F == 0.0 || fabs(dmu) <= newton_tol<ST, LOOSE>(mu)) {   // the error left after this step is O(dmu^2)
             mu -= (F == 0.0) ? 0.0 : dmu;
             conv = true;
@@ -408,9 +422,7 @@ __device__ __forceinline__ double invert_g2(double target, unsigned &flags) {
     double lo = -40.0, hi = (ST == RLBM_BE) ? LOG_ZC_BE : FD_MU_MIN + (FD_NC - 0.5) * FD_DMU;
     double mu = (ST == RLBM_BE) ? -0.6931471805599453 : 0.0;
     if (ST == RLBM_BE) {
-        double g[7];
-        gvals<ST, 1, 2>(LOG_ZC_BE, g, flags);
-        if (!(target < g[2])) {   // density above the condensation bound at this theta
+        if (!(target < G2_ZC_BE)) {   // density above the condensation bound at this theta
             flags |= RLBM_FLAG_CONDENSED;
             return LOG_ZC_BE;
         }
@@ -474,7 +486,7 @@ __device__ __forceinline__ void state_from_moments(const Mom &m, Macro &M, unsig
         double mu0 = (ST == RLBM_BE) ? -0.6931471805599453 : 0.0;
         if (a.guess == RLBM_GUESS_MLP) mu0 = (double)rlbm_mlp::eval(a.mlp, logf((float)r));
         const double mu = invert_h<ST, LOOSE>(r, mu0, flags, iters);
-        gvals<ST, 1, 6>(mu, M.g, flags);
+        gvals<ST, 1, 6, LOOSE>(mu, M.g, flags);
         M.z = exp(mu);
         M.theta = 0.5 * (M.g[2] / M.g[3]) * (M.eps / M.n);
     }

@@ -51,6 +51,10 @@ BE_MU_SPLIT = -1.0                                   # log series on [-1, 0)
 BE_MU_MIN, BE_DMU = -12.0, 0.125
 BE_NC = int(round((BE_MU_SPLIT - BE_MU_MIN) / BE_DMU)) + 1   # centres -12 .. -1
 BE_NZ = 24                                           # terms of the series about mu = 0
+# Shorter sums for FP32 / FP16 population storage, where g to 1e-11 relative is far
+# below the populations' rounding; check_loose_truncation bounds the omitted tail.
+NT_LOOSE = 9
+BE_NZ_LOOSE = 15
 
 
 def _omega(stats, p):
@@ -173,6 +177,30 @@ def g_taylor_table(xi, centres):
     return rows
 
 
+def check_loose_truncation(fd_rows, be_rows, bound=1e-11):
+    """Largest relative size of the tail that NT_LOOSE Taylor terms (tables) and
+    BE_NZ_LOOSE series terms (about mu = 0) leave out, over each interval a centre
+    serves; raises if above bound.  The tail is taken as twice its first term (the
+    terms fall by a factor below 1/2 from there on)."""
+    worst = 0.0
+    for rows, dmu in ((fd_rows, FD_DMU), (be_rows, BE_DMU)):
+        h = mp.mpf(dmu) / 2
+        for row in rows:
+            for m in range(1, 7):
+                gm = row[6 - m]
+                first = abs(row[6 - m + NT_LOOSE]) * h ** NT_LOOSE / mp.factorial(NT_LOOSE)
+                worst = max(worst, float(2 * first / (gm * (1 - 2 * h))))
+    with mp.workdps(30):
+        mu = -(mp.mpf(-BE_MU_SPLIT) + mp.mpf(BE_DMU) / 2)
+        for m in range(1, 7):
+            k = BE_NZ_LOOSE
+            first = abs(mp.zeta(m - k)) * abs(mu) ** k / mp.factorial(k)
+            worst = max(worst, float(2 * first / mp.polylog(m, mp.exp(mu))))
+    if worst > bound:
+        raise ValueError("shortened g sums leave %.3g relative" % worst)
+    return worst
+
+
 def _fmt(x):
     return repr(float(x))
 
@@ -188,8 +216,15 @@ def emit(path):
     lines.append("constexpr double BE_MU_MIN = %r, BE_DMU = %r, BE_MU_SPLIT = %r; constexpr int BE_NC = %d;"
                  % (BE_MU_MIN, BE_DMU, BE_MU_SPLIT, BE_NC))
     lines.append("constexpr int BE_NZ = %d;" % BE_NZ)
+    lines.append("constexpr int NT_LOOSE = %d, BE_NZ_LOOSE = %d;   // terms when 1e-11 relative suffices"
+                 % (NT_LOOSE, BE_NZ_LOOSE))
     with mp.workdps(DPS):
         lines.append("constexpr double LOG_ZC_BE = %s;" % _fmt(mp.log(ZC)))
+        g1c, g2c = mp.polylog(1, ZC), mp.polylog(2, ZC)
+        g3c = mp.polylog(3, ZC)
+        lines.append("// Bose-Einstein g_1, g_2 and h = g_2^3 / g_3^2 at the condensation fugacity z_c")
+        lines.append("constexpr double G1_ZC_BE = %s, G2_ZC_BE = %s, H_ZC_BE = %s;"
+                     % (_fmt(g1c), _fmt(g2c), _fmt(g2c ** 3 / g3c ** 2)))
     lines.append("")
 
     p_all, w_all, E_all = [], [], []
@@ -231,6 +266,7 @@ def emit(path):
     be_c = [BE_MU_MIN + i * BE_DMU for i in range(BE_NC)]
     fd = g_taylor_table(1, fd_c)
     be = g_taylor_table(-1, be_c)
+    print("shortened g sums: tail <= %.2e relative" % check_loose_truncation(fd, be))
     lines.append("// g_m(mu_c) for m = 6, 5, ..., 6-NG+1 at centres mu_c = MU_MIN + i DMU")
     lines.append("__constant__ double FD_TAB[%d][%d] = {%s};" % (FD_NC, NG, ", ".join(
         "{" + ", ".join(_fmt(x) for x in r) + "}" for r in fd)))
