@@ -158,6 +158,15 @@ int rlbm_moments_grid(rlbm_ctx *ctx, int32_t g, const rlbm_out_fields *out);
  * stream.  Returns RLBM_EDOMAIN if the status word has bits set (then clears it). */
 int rlbm_moments(rlbm_ctx *ctx, const rlbm_out_fields *out);
 
+/* Diagonal x components of the non-equilibrium tensors of ranks 2 to 5 (Eq.
+ * tensors-eq), pi^{x..x} = sum_i (f_i - f^eq_i) (p_i^x)^r, of grid g's current state:
+ * f are the pre-collision populations the next step would see and f^eq the
+ * equilibrium of the expansion order in use at the cell's own (theta, z, u).
+ * Outputs are device arrays of nx*ny doubles (y-major); a NULL one is skipped.
+ * Synchronises the stream; errors as rlbm_moments. */
+int rlbm_noneq_tensors(rlbm_ctx *ctx, int32_t g, double *pi_xx, double *pi_xxx, double *pi_xxxx,
+                       double *pi_xxxxx);
+
 /* 0 if f_a holds the current state, 1 if f_b does. */
 int rlbm_state_index(const rlbm_ctx *ctx);
 

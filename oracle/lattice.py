@@ -193,6 +193,19 @@ def fields(fstar, p: Params):
                 ux=mac["ux"], uy=mac["uy"], qx=qx, qy=qy, ok=mac["ok"])
 
 
+def noneq_tensors(fstar, p: Params):
+    """Diagonal x components of the non-equilibrium tensors of ranks 2..5 (Eq.
+    tensors-eq): {r: sum_i (f_i - f^eq_i) (p_i^x)^r}, for the pre-collision populations
+    the next step would see and the equilibrium of order p.order at each cell's own
+    (theta, z, u)."""
+    f = stream(fstar, p)
+    mac = macroscopic(f, p)
+    feq = equilibrium_state(p, mac["theta"], mac["g"], mac["ux"], mac["uy"])
+    px = quadrature.vectors(p.stats)["px"]
+    d = f - feq
+    return {r: np.tensordot(px ** r, d, axes=(0, 0)) for r in (2, 3, 4, 5)}
+
+
 def init_state(p: Params, theta, ux, uy, n=None, z=None):
     """Initial post-collision state f* = f^eq from (n or z, theta, u)."""
     theta = np.asarray(theta, dtype=np.float64)

@@ -87,6 +87,7 @@ struct KArgs {
     int given_z;
     // field outputs
     double *o_n, *o_eps, *o_theta, *o_z, *o_ux, *o_uy, *o_qx, *o_qy;
+    double *o_pi[4];             // non-equilibrium tensors pi^{x..x} of rank 2..5
 };
 
 // ---------------------------------------------------------------- tile mapping
@@ -891,6 +892,59 @@ __global__ __launch_bounds__(256) void k_moments(KArgs a) {
     report(a.status, flags);
 }
 
+// sum_i f_i (p_i^x)^r for r = 2..5, in FP64: p^x = p_k cos(phi_n).
+template <int ST, typename R>
+__device__ __forceinline__ void px_powers(const R (&f)[72], double (&o)[4]) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) o[r] = 0.0;
+#pragma unroll
+    for (int n = 0; n < 12; ++n) {
+        if (n == 3 || n == 9) continue;   // cos(phi_n) = 0
+        double a[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const double p = P_SHELL[ST][k], v = (double)f[6 * n + k];
+            a[0] += v * (p * p);
+            a[1] += v * (p * p * p);
+            a[2] += v * (p * p * p * p);
+            a[3] += v * (p * p * p * p * p);
+        }
+        const double c = cdir(n);
+        o[0] += a[0] * (c * c);
+        o[1] += a[1] * (c * c * c);
+        o[2] += a[2] * (c * c * c * c);
+        o[3] += a[3] * (c * c * c * c * c);
+    }
+}
+
+// Diagonal x components of the non-equilibrium tensors, pi^{x..x} = sum_i (f_i -
+// f^eq_i) (p_i^x)^r for r = 2..5 (Eq. tensors-eq), of the pre-collision populations
+// the next step would see; f^eq is the order-N equilibrium of the cell's own state.
+template <int ST, typename S, typename R, int N>
+__global__ __launch_bounds__(256) void k_noneq(KArgs a) {
+    int x, y;
+    if (!cell_of(a, x, y)) return;
+    unsigned flags = 0;
+    int xl, xr, yd, yu;
+    neighbours(a, x, y, xl, xr, yd, yu);
+    R f[72];
+    if constexpr (std::is_same<S, Dev16>::value) pull_dev<ST>(a.fin, a.plane, a.nx, x, y, xl, xr, yd, yu, f);
+    else pull<S, R>((const S *)a.fin, a.plane, a.nx, x, y, xl, xr, yd, yu, f);
+    const Mom m = moments<ST, R>(f);
+    Macro M;
+    int iters;
+    state_from_moments<ST, sizeof(R) == 4>(m, M, flags, a, iters);
+    double sf[4], se[4];
+    px_powers<ST, R>(f, sf);
+    equilibrium_relax<ST, false, R, N>(M, 1.0, f);   // f <- f^eq
+    px_powers<ST, R>(f, se);
+    const int off = y * a.nx + x;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        if (a.o_pi[r]) a.o_pi[r][off] = sf[r] - se[r];
+    report(a.status, flags);
+}
+
 template <int ST, typename S, typename R, int N = 5>
 __global__ __launch_bounds__(256) void k_init(KArgs a) {
     int x, y;
@@ -955,6 +1009,20 @@ KFn pick_order(int which, int st, int prec, int order) {
     if (order == 2) return pick_lo<2>(which, prec);
     if (order == 3) return pick_lo<3>(which, prec);
     return pick_lo<4>(which, prec);
+}
+
+template <int ST, int N>
+KFn noneq_kernel(int prec) {
+    if constexpr (N < 5) return prec == RLBM_FP64 ? k_noneq<ST, double, double, N> : k_noneq<ST, float, float, N>;
+    else return prec == RLBM_FP64 ? k_noneq<ST, double, double, N>
+              : prec == RLBM_FP32 ? k_noneq<ST, float, float, N> : k_noneq<ST, Dev16, float, N>;
+}
+
+KFn pick_noneq(int st, int prec, int order) {
+    if (st == RLBM_FD) return noneq_kernel<RLBM_FD, 5>(prec);
+    if (st == RLBM_BE) return noneq_kernel<RLBM_BE, 5>(prec);
+    return order == 2 ? noneq_kernel<RLBM_MJ, 2>(prec) : order == 3 ? noneq_kernel<RLBM_MJ, 3>(prec)
+         : order == 4 ? noneq_kernel<RLBM_MJ, 4>(prec) : noneq_kernel<RLBM_MJ, 5>(prec);
 }
 
 BFn pick_batch(int st, int prec) {
@@ -1400,6 +1468,22 @@ int rlbm_inversion_samples(rlbm_ctx *c, float *x, float *t) {
 }
 
 int rlbm_moments(rlbm_ctx *c, const rlbm_out_fields *o) { return rlbm_moments_grid(c, 0, o); }
+
+int rlbm_noneq_tensors(rlbm_ctx *c, int32_t g, double *pi_xx, double *pi_xxx, double *pi_xxxx, double *pi_xxxxx) {
+    if (!c || g < 0 || g >= (int)c->base.size()) return RLBM_EINVAL;
+    KArgs a = c->base[g];
+    set_tiles(a, 32, 8);
+    a.fin = c->cur ? c->p[g].f_b : c->p[g].f_a;
+    a.o_pi[0] = pi_xx;
+    a.o_pi[1] = pi_xxx;
+    a.o_pi[2] = pi_xxxx;
+    a.o_pi[3] = pi_xxxxx;
+    a.stats = nullptr;
+    hipLaunchKernelGGL(pick_noneq(c->p[0].stats, c->p[0].precision, c->p[0].order), dim3(8 * a.per_xcd), dim3(256), 0,
+                       c->stream, a);
+    if (hipGetLastError() != hipSuccess) return RLBM_EHIP;
+    return rlbm_sync(c);
+}
 
 int rlbm_state_index(const rlbm_ctx *c) { return c ? c->cur : -1; }
 

@@ -84,6 +84,7 @@ def lib():
         L.rlbm_moments_grid.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(OutFields)]
         L.rlbm_inversion_stats.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)]
         L.rlbm_inversion_samples.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        L.rlbm_noneq_tensors.argtypes = [ctypes.c_void_p, ctypes.c_int32] + [ctypes.c_void_p] * 4
         L.rlbm_mlp_workspace_bytes.argtypes = [ctypes.c_int64]
         L.rlbm_mlp_workspace_bytes.restype = ctypes.c_uint64
         vp = ctypes.c_void_p
@@ -175,6 +176,14 @@ class Sim:
         rc = lib().rlbm_moments(self.ctx, ctypes.byref(of))
         if check:
             _check(rc, "rlbm_moments")
+        return out
+
+    def noneq_tensors(self, check=True):
+        """{r: pi^{x..x} of rank r} for r = 2..5 (float64 (ny, nx) tensors)."""
+        out = {r: torch.empty((self.ny, self.nx), dtype=torch.float64, device=self.f[0].device) for r in (2, 3, 4, 5)}
+        rc = lib().rlbm_noneq_tensors(self.ctx, 0, *(_ptr(out[r]) for r in (2, 3, 4, 5)))
+        if check:
+            _check(rc, "rlbm_noneq_tensors")
         return out
 
     def sync(self):
@@ -317,6 +326,15 @@ class Batch:
         rc = lib().rlbm_moments_grid(self.ctx, int(g), ctypes.byref(of))
         if check:
             _check(rc, "rlbm_moments_grid")
+        return out
+
+    def noneq_tensors(self, g, check=True):
+        p = self.params[g]
+        ny, nx = int(p["ny"]), int(p["nx"])
+        out = {r: torch.empty((ny, nx), dtype=torch.float64, device=self.f[g][0].device) for r in (2, 3, 4, 5)}
+        rc = lib().rlbm_noneq_tensors(self.ctx, int(g), *(_ptr(out[r]) for r in (2, 3, 4, 5)))
+        if check:
+            _check(rc, "rlbm_noneq_tensors")
         return out
 
     def sync(self):

@@ -1,0 +1,73 @@
+"""Non-equilibrium tensors pi^{x..x} of ranks 2..5 (Eq. tensors-eq) from the HIP
+path, against the FP64 oracle on the same seeded state.
+
+Bars are relative to the per-cell scale sum_i |f_i| |p_i^x|^r, the size of the two
+sums whose difference pi is.  FP64 populations: 2e-13 for every rank after 6 steps
+(each sum carries ~1e-15 relative rounding per step on either side; the errors seen
+stay below 2.5e-14).  FP32 populations: 2e-6 for every rank (storage rounding 2^-24
+per step plus the FP32 equilibrium synthesis; seen: below 5e-7)."""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import lattice as L
+from oracle import quadrature as Q
+
+pytestmark = pytest.mark.gpu
+
+BAR_FP64 = {2: 2e-13, 3: 2e-13, 4: 2e-13, 5: 2e-13}
+BAR_FP32 = {2: 2e-6, 3: 2e-6, 4: 2e-6, 5: 2e-6}
+
+
+@pytest.fixture(scope="module")
+def rl():
+    from paper_1709_09073_amd import rlbm
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return rlbm
+
+
+def _case(rl, stats, precision, order, steps, nx=40, ny=24, seed=21):
+    fields = workloads.smooth_random(nx, ny, seed, stats=stats, amp_theta=0.2, amp_u=0.2)
+    params = dict(nx=nx, ny=ny, stats=stats, order=order, precision=precision, tau_mode="const", tau=0.8,
+                  bc=("periodic",) * 4)
+    sim = rl.Sim(params, {k: v.cuda() for k, v in fields.items()})
+    sim.step(steps)
+    got = {r: v.cpu().numpy() for r, v in sim.noneq_tensors().items()}
+    sim.close()
+    op = L.Params(stats=stats, nx=nx, ny=ny, tau=0.8, order=order)
+    f0 = {k: v.numpy() for k, v in fields.items()}
+    f = L.run(L.init_state(op, f0["theta"], f0["ux"], f0["uy"], z=f0["z"]), op, steps)
+    ref = L.noneq_tensors(f, op)
+    fs = L.stream(f, op)
+    px = Q.vectors(stats)["px"]
+    scale = {r: np.tensordot(np.abs(px) ** r, np.abs(fs), axes=(0, 0)) for r in ref}
+    return got, ref, scale
+
+
+def _check(got, ref, scale, bars, ctx):
+    for r in (2, 3, 4, 5):
+        err = (np.abs(got[r] - ref[r]) / scale[r]).max()
+        size = (np.abs(ref[r]) / scale[r]).max()
+        print(f"  {ctx}: rank {r} err {err:.2e} (bar {bars[r]:.0e}), |pi|/scale up to {size:.1e}")
+        assert err <= bars[r], (ctx, r, err)
+        assert size > 100 * bars[r]   # pi itself is well above the bar
+
+
+@pytest.mark.parametrize("stats", ["MJ", "FD", "BE"])
+def test_fifth_order_fp64(rl, stats):
+    got, ref, scale = _case(rl, stats, "fp64", 5, 6)
+    _check(got, ref, scale, BAR_FP64, f"{stats} N=5 fp64")
+
+
+@pytest.mark.parametrize("order", [2, 3, 4])
+def test_lower_orders_fp64(rl, order):
+    got, ref, scale = _case(rl, "MJ", "fp64", order, 6)
+    _check(got, ref, scale, BAR_FP64, f"MJ N={order} fp64")
+
+
+@pytest.mark.parametrize("stats", ["MJ", "FD"])
+def test_fifth_order_fp32(rl, stats):
+    got, ref, scale = _case(rl, stats, "fp32", 5, 6)
+    _check(got, ref, scale, BAR_FP32, f"{stats} N=5 fp32")

@@ -92,4 +92,5 @@ def test_null_context_calls(rl):
     assert L.rlbm_step(None, 1) == rl.RLBM_EINVAL
     assert L.rlbm_sync(None) == rl.RLBM_EINVAL
     assert L.rlbm_state_index(None) == -1
+    assert L.rlbm_noneq_tensors(None, 0, None, None, None, None) == rl.RLBM_EINVAL
     L.rlbm_free(None)
