@@ -166,6 +166,14 @@ class Sim:
         """The tensor (72, ny, nx) holding the current post-collision populations."""
         return self.f[lib().rlbm_state_index(self.ctx)]
 
+    def load_state(self, saved):
+        """Resume from a saved post-collision state (a tensor like state()): the
+        populations are the whole state, so copying them into the current buffer
+        restarts the run; the step counter is not part of the physics."""
+        self.sync()
+        self.state().copy_(saved)
+        torch.cuda.synchronize(self.state().device)
+
     @property
     def steps_done(self):
         return lib().rlbm_steps_done(self.ctx)
