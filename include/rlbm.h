@@ -70,7 +70,10 @@ enum rlbm_tau_mode { RLBM_TAU_CONST = 0, RLBM_TAU_INV_THETA = 1 };  /* tau, or t
 enum rlbm_bc {
     RLBM_BC_PERIODIC = 0, /* wrap (both sides of an axis must be periodic) */
     RLBM_BC_OPEN = 1,     /* zero gradient: a pull from outside takes the nearest edge cell */
-    RLBM_BC_WALL_T = 2    /* fixed-temperature wall cell on the edge column (x sides only) */
+    RLBM_BC_WALL_T = 2,   /* fixed-temperature wall cell on the edge column (x sides only) */
+    RLBM_BC_WALL_NEQ = 3  /* wall node on the edge row (y sides only, Sec. 3.4): equilibrium of
+                             (wall_n, wall_theta, u = 0) plus the post-collision non-equilibrium
+                             part f* - f^eq of the nearest fluid row */
 };
 enum rlbm_guess { RLBM_GUESS_FIXED = 0, RLBM_GUESS_MLP = 1 };       /* FD/BE inversion start */
 
@@ -98,8 +101,12 @@ typedef struct rlbm_params {
                                 (F16DEV: 180*nx*ny bytes each, 4-byte aligned) */
     void *stream;            /* hipStream_t, NULL = default stream */
     int32_t tile_x, tile_y;  /* cells per workgroup tile, tile_x * tile_y = 256 with tile_x a power
-                                of two >= 16; 0, 0 = automatic (32 x 8; 64 x 4 or 128 x 2 for ny < 8, 4) */
+                                of two >= 16; 0, 0 = automatic (32 x 8; 128 x 2 when nx >= 4096;
+                                64 x 4 or 128 x 2 for ny < 8, 4) */
     int32_t collect_stats;   /* 1: count Newton iterations of the FD/BE inversion (rlbm_inversion_stats) */
+    double force[2];         /* constant acceleration (a_x, a_y) applied by momentum update: the
+                                collision uses u + a tau (Sec. 3.4); 0, 0 = none */
+    double wall_n, wall_theta; /* imposed density and temperature of RLBM_BC_WALL_NEQ sides */
 } rlbm_params;
 
 typedef struct rlbm_init_fields {

@@ -22,7 +22,11 @@ cell (x, y) at integer coordinates x = 0..nx-1, y = 0..ny-1.
 Boundary rules per side: 'periodic' (wrap), 'open' (a pull from outside the grid
 takes the nearest cell of the grid: zero-gradient), 'wall' (fixed-temperature wall
 cell on the edge column; x sides only; its own pull is clamped like 'open' and then
-replaced in step 9).
+replaced in step 9), 'wall_neq' (y sides only: the edge row is a wall node whose
+state is the equilibrium of an imposed (n, theta, u = 0) plus the non-equilibrium
+part extrapolated from the nearest fluid row, Sec. 3.4; pulls clamp like 'open').
+
+Forced flow (Sec. 3.4): with p.force = (a_x, a_y) the collision uses u + a tau.
 """
 from dataclasses import dataclass, field
 
@@ -47,6 +51,8 @@ class Params:
     bc: dict = field(default_factory=lambda: dict(xlo="periodic", xhi="periodic",
                                                   ylo="periodic", yhi="periodic"))
     theta_wall: dict = field(default_factory=lambda: dict(xlo=1.0, xhi=1.0))
+    force: tuple = (0.0, 0.0)   # constant acceleration (a_x, a_y), momentum update u + a tau
+    wall_eq: dict = field(default_factory=lambda: dict(n=1.0, theta=1.0))   # 'wall_neq' sides, u = 0
 
 
 def _src(idx, d, L, lo, hi):
@@ -160,16 +166,41 @@ def _wall_feq(p: Params, mac, side):
     return equilibrium_state(p, th, g, ux, uy)
 
 
+def forced(mac, tau, p: Params):
+    """Momentum update of the forced flow (Sec. 3.4): the collision sees u + a tau
+    (and its gamma) in place of the Landau velocity; theta, z and n are unchanged."""
+    ax, ay = p.force
+    if ax == 0.0 and ay == 0.0:
+        return mac
+    ux, uy = mac["ux"] + ax * tau, mac["uy"] + ay * tau
+    return dict(mac, ux=ux, uy=uy, gamma=1.0 / np.sqrt(1.0 - (ux * ux + uy * uy)))
+
+
+def _neq_wall_feq(p: Params):
+    """f^eq at the imposed wall state (n, theta from p.wall_eq, u = 0), shape (72,)."""
+    th = np.array(p.wall_eq["theta"], dtype=np.float64)
+    z = gfunc.z_from_n_theta(p.stats, np.array(p.wall_eq["n"], dtype=np.float64), th)
+    return equilibrium_state(p, th, gfunc.g_all(p.stats, z), 0.0, 0.0)
+
+
 def step(fstar, p: Params):
-    """One time step: returns (new post-collision state, macroscopic dict of this step)."""
+    """One time step: returns (new post-collision state, macroscopic dict of this step).
+
+    Walls with non-equilibrium extrapolation ('wall_neq', y sides, Sec. 3.4): the
+    wall row's post-collision state is the equilibrium of the imposed wall state plus
+    the post-collision non-equilibrium part f* - f^eq of the nearest fluid row."""
     f = stream(fstar, p)
     mac = macroscopic(f, p)
     tau = relaxation_time(mac["theta"], p)
-    feq = equilibrium_state(p, mac["theta"], mac["g"], mac["ux"], mac["uy"])
-    out = collide(f, feq, mac, tau, p.stats)
+    cm = forced(mac, tau, p)
+    feq = equilibrium_state(p, cm["theta"], cm["g"], cm["ux"], cm["uy"])
+    out = collide(f, feq, cm, tau, p.stats)
     for side, col in (("xlo", 0), ("xhi", p.nx - 1)):
         if p.bc[side] == "wall":
             out[:, :, col] = _wall_feq(p, mac, side)
+    for side, row, nb in (("ylo", 0, 1), ("yhi", p.ny - 1, p.ny - 2)):
+        if p.bc[side] == "wall_neq":
+            out[:, row, :] = _neq_wall_feq(p)[:, None] + (out[:, nb, :] - feq[:, nb, :])
     return out, mac
 
 

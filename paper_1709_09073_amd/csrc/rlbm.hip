@@ -43,8 +43,10 @@
 #define RLBM_BATCH_WAVES_FDBE 2      // the batch kernel spills at 3
 #endif
 // FP64 populations need about twice the registers: no occupancy target (no spills)
-#define RLBM_STEP_BOUNDS(ST, R) \
-    __launch_bounds__(256, sizeof(R) == 8 ? 1 : ((ST) == RLBM_MJ ? RLBM_STEP_WAVES_PER_SIMD : RLBM_STEP_WAVES_FDBE))
+// (the forced / non-equilibrium-wall variant carries a second equilibrium state: 2 waves)
+#define RLBM_STEP_BOUNDS(ST, R, FORCED) \
+    __launch_bounds__(256, sizeof(R) == 8 ? 1 : (FORCED) ? 2 \
+                           : ((ST) == RLBM_MJ ? RLBM_STEP_WAVES_PER_SIMD : RLBM_STEP_WAVES_FDBE))
 #define RLBM_BATCH_BOUNDS(ST, R) \
     __launch_bounds__(256, sizeof(R) == 8 ? 1 : ((ST) == RLBM_MJ ? RLBM_BATCH_WAVES_MJ : RLBM_BATCH_WAVES_FDBE))
 
@@ -77,6 +79,8 @@ struct KArgs {
     int tau_mode;
     double tau, tau_a, tau_b;
     double th_wall_lo, th_wall_hi;
+    double force_x, force_y;     // momentum-update acceleration (forced kernels)
+    double wall_n, wall_theta;   // state imposed on RLBM_BC_WALL_NEQ rows
     int guess;
     const float *mlp;
     unsigned *status;
@@ -524,7 +528,9 @@ __device__ __forceinline__ void state_from_z_theta(double z, double theta, Macro
 // ---------------------------------------------------------------- equilibrium + relaxation
 // f^eq_{s,n} = sum_j r_j(s) A_{j,n};  r_j(s) = sum_k E^(j)_{s,k} G_k P_kj(u^2) (FP64),
 // A_{j,n} = Re[(u_x + i u_y)^j e^{-i j phi_n}], G_k = k! g_{k+1} theta^{k+1} gamma^k.
-// If COLLIDE: f <- f + omega_n (f^eq - f), omega_n = gamma (1 - v_n.u) / tau; else f <- f^eq.
+// MODE: EQ_SET f <- f^eq; EQ_COLLIDE f <- f + omega_n (f^eq - f) with
+// omega_n = gamma (1 - v_n.u) / tau; EQ_NEQ f <- (1 - omega_n)(f - f^eq), the part
+// f* - f^eq a collision leaves; EQ_ADD f <- f + f^eq.
 // Projector table of expansion order N (5 for every statistic; 2..4 for Maxwell-Juttner).
 template <int ST, int N>
 __device__ __forceinline__ constexpr double emat(int pair, int shell) {
@@ -532,8 +538,11 @@ __device__ __forceinline__ constexpr double emat(int pair, int shell) {
     else return EMAT_LO[N - 2][pair][shell];
 }
 
-template <int ST, bool COLLIDE, typename R, int N = 5>
+enum { EQ_SET = 0, EQ_COLLIDE = 1, EQ_NEQ = 2, EQ_ADD = 3 };
+
+template <int ST, int MODE, typename R, int N = 5>
 __device__ __forceinline__ void equilibrium_relax(const Macro &M, double tau, R (&f)[72]) {
+    constexpr bool COLLIDE = MODE == EQ_COLLIDE || MODE == EQ_NEQ;
     static_assert(N == 5 || (ST == RLBM_MJ && N >= 2 && N <= 4), "lower orders are tabulated for MJ");
     const double u2 = M.ux * M.ux + M.uy * M.uy;
     double G[6];
@@ -606,9 +615,15 @@ __device__ __forceinline__ void equilibrium_relax(const Macro &M, double tau, R 
             const R fe0 = ev + od, fe1 = ev - od;
             R &a = f[6 * n + s];
             R &b = f[6 * (n + 6) + s];
-            if constexpr (COLLIDE) {
+            if constexpr (MODE == EQ_COLLIDE) {
                 a = a + om[n] * (fe0 - a);
                 b = b + om[n + 6] * (fe1 - b);
+            } else if constexpr (MODE == EQ_NEQ) {
+                a = (a - fe0) - om[n] * (a - fe0);
+                b = (b - fe1) - om[n + 6] * (b - fe1);
+            } else if constexpr (MODE == EQ_ADD) {
+                a = a + fe0;
+                b = b + fe1;
             } else {
                 a = fe0;
                 b = fe1;
@@ -784,17 +799,25 @@ __device__ __forceinline__ void report(unsigned *status, unsigned flags) {
 
 // ---------------------------------------------------------------- kernels
 // One fused update of cell (x, y) of the grid described by a.
-template <int ST, typename S, typename R, int N = 5>
+// FORCED: the variant for forced flows and RLBM_BC_WALL_NEQ rows (Sec. 3.4).
+template <int ST, typename S, typename R, int N = 5, bool FORCED = false>
 __device__ __forceinline__ void step_cell(const KArgs &a, int x, int y) {
     unsigned flags = 0;
     const bool wall_lo = (a.bc_xlo == RLBM_BC_WALL_T) && x == 0;
     const bool wall_hi = (a.bc_xhi == RLBM_BC_WALL_T) && x == a.nx - 1;
     const int xe = wall_lo ? 1 : (wall_hi ? a.nx - 2 : x);   // wall cells read their fluid neighbour
+    bool neq_lo = false, neq_hi = false;
+    int ye = y;
+    if constexpr (FORCED) {
+        neq_lo = (a.bc_ylo == RLBM_BC_WALL_NEQ) && y == 0;
+        neq_hi = (a.bc_yhi == RLBM_BC_WALL_NEQ) && y == a.ny - 1;
+        ye = neq_lo ? 1 : (neq_hi ? a.ny - 2 : y);   // wall rows update their fluid neighbour first
+    }
     int xl, xr, yd, yu;
-    neighbours(a, xe, y, xl, xr, yd, yu);
+    neighbours(a, xe, ye, xl, xr, yd, yu);
     R f[72];
-    if constexpr (std::is_same<S, Dev16>::value) pull_dev<ST>(a.fin, a.plane, a.nx, xe, y, xl, xr, yd, yu, f);
-    else pull<S, R>((const S *)a.fin, a.plane, a.nx, xe, y, xl, xr, yd, yu, f);
+    if constexpr (std::is_same<S, Dev16>::value) pull_dev<ST>(a.fin, a.plane, a.nx, xe, ye, xl, xr, yd, yu, f);
+    else pull<S, R>((const S *)a.fin, a.plane, a.nx, xe, ye, xl, xr, yd, yu, f);
     const Mom m = moments<ST, R>(f);
     Macro M;
     int iters;
@@ -813,21 +836,42 @@ __device__ __forceinline__ void step_cell(const KArgs &a, int x, int y) {
         // zeroth-order extrapolation of n and u, fixed wall temperature
         const double n = M.n;
         state_from_n_theta<ST>(n, wall_lo ? a.th_wall_lo : a.th_wall_hi, M, flags);
-        equilibrium_relax<ST, false, R, N>(M, 1.0, f);
+        equilibrium_relax<ST, EQ_SET, R, N>(M, 1.0, f);
     } else {
         const double tau = (a.tau_mode == RLBM_TAU_CONST) ? a.tau : a.tau_a / M.theta + a.tau_b;
-        equilibrium_relax<ST, true, R, N>(M, tau, f);
+        if constexpr (FORCED) {
+            // momentum update: the collision sees u + a tau
+            M.ux += a.force_x * tau;
+            M.uy += a.force_y * tau;
+            if (!(M.ux * M.ux + M.uy * M.uy < 1.0)) {
+                flags |= RLBM_FLAG_SUPERLUMINAL;
+                M.ux = M.uy = 0.0;
+            }
+            M.ga = 1.0 / sqrt(1.0 - (M.ux * M.ux + M.uy * M.uy));
+            if (neq_lo || neq_hi) {
+                // wall row: f^eq(wall_n, wall_theta, u = 0) + (f* - f^eq) of the fluid neighbour
+                equilibrium_relax<ST, EQ_NEQ, R, N>(M, tau, f);
+                state_from_n_theta<ST>(a.wall_n, a.wall_theta, M, flags);
+                M.ux = M.uy = 0.0;
+                M.ga = 1.0;
+                equilibrium_relax<ST, EQ_ADD, R, N>(M, 1.0, f);
+            } else {
+                equilibrium_relax<ST, EQ_COLLIDE, R, N>(M, tau, f);
+            }
+        } else {
+            equilibrium_relax<ST, EQ_COLLIDE, R, N>(M, tau, f);
+        }
     }
     if constexpr (std::is_same<S, Dev16>::value) store_dev<ST>(a.fout, a.plane, y * a.nx + x, f);
     else store<S, R>((S *)a.fout, a.plane, y * a.nx + x, f);
     report(a.status, flags);
 }
 
-template <int ST, typename S, typename R, int N = 5>
-__global__ RLBM_STEP_BOUNDS(ST, R) void k_step(KArgs a) {
+template <int ST, typename S, typename R, int N = 5, bool FORCED = false>
+__global__ RLBM_STEP_BOUNDS(ST, R, FORCED) void k_step(KArgs a) {
     int x, y;
     if (!cell_of(a, x, y)) return;
-    step_cell<ST, S, R, N>(a, x, y);
+    step_cell<ST, S, R, N, FORCED>(a, x, y);
 }
 
 // Many grids in one launch.  The tiles of all grids are numbered consecutively
@@ -936,7 +980,7 @@ __global__ __launch_bounds__(256) void k_noneq(KArgs a) {
     state_from_moments<ST, sizeof(R) == 4>(m, M, flags, a, iters);
     double sf[4], se[4];
     px_powers<ST, R>(f, sf);
-    equilibrium_relax<ST, false, R, N>(M, 1.0, f);   // f <- f^eq
+    equilibrium_relax<ST, EQ_SET, R, N>(M, 1.0, f);   // f <- f^eq
     px_powers<ST, R>(f, se);
     const int off = y * a.nx + x;
 #pragma unroll
@@ -964,7 +1008,7 @@ __global__ __launch_bounds__(256) void k_init(KArgs a) {
     if (a.given_z) state_from_z_theta<ST>(a.i_z[off], th, M, flags);
     else state_from_n_theta<ST>(a.i_n[off], th, M, flags);
     R f[72];
-    equilibrium_relax<ST, false, R, N>(M, 1.0, f);
+    equilibrium_relax<ST, EQ_SET, R, N>(M, 1.0, f);
     if constexpr (std::is_same<S, Dev16>::value) store_dev<ST>(a.fout, a.plane, off, f);
     else store<S, R>((S *)a.fout, a.plane, off, f);
     report(a.status, flags);
@@ -1003,6 +1047,17 @@ KFn pick_lo(int which, int prec) {
 }
 
 KFn pick(int which, int st, int prec);
+
+// forced flow / non-equilibrium walls: order 5, FP64 or FP32 populations
+KFn pick_forced(int st, int prec) {
+    if (st == RLBM_MJ) return prec == RLBM_FP64 ? k_step<RLBM_MJ, double, double, 5, true> : k_step<RLBM_MJ, float, float, 5, true>;
+    if (st == RLBM_FD) return prec == RLBM_FP64 ? k_step<RLBM_FD, double, double, 5, true> : k_step<RLBM_FD, float, float, 5, true>;
+    return prec == RLBM_FP64 ? k_step<RLBM_BE, double, double, 5, true> : k_step<RLBM_BE, float, float, 5, true>;
+}
+
+bool is_forced(const rlbm_params &p) {
+    return p.force[0] != 0.0 || p.force[1] != 0.0 || p.bc[2] == RLBM_BC_WALL_NEQ || p.bc[3] == RLBM_BC_WALL_NEQ;
+}
 
 KFn pick_order(int which, int st, int prec, int order) {
     if (order == 5 || which == 1) return pick(which, st, prec);
@@ -1086,7 +1141,15 @@ int validate(const rlbm_params *p) {
         return RLBM_EINVAL;
     }
     for (int i = 0; i < 4; ++i)
-        if (p->bc[i] < RLBM_BC_PERIODIC || p->bc[i] > RLBM_BC_WALL_T) return RLBM_EINVAL;
+        if (p->bc[i] < RLBM_BC_PERIODIC || p->bc[i] > RLBM_BC_WALL_NEQ) return RLBM_EINVAL;
+    if (p->bc[0] == RLBM_BC_WALL_NEQ || p->bc[1] == RLBM_BC_WALL_NEQ) return RLBM_EINVAL;   // y sides only
+    if (!std::isfinite(p->force[0]) || !std::isfinite(p->force[1])) return RLBM_EINVAL;
+    if (is_forced(*p)) {
+        if (p->order != 5 || p->precision == RLBM_F16DEV) return RLBM_ENOTIMPL;
+        if ((p->bc[2] == RLBM_BC_WALL_NEQ || p->bc[3] == RLBM_BC_WALL_NEQ) &&
+            (p->ny < 3 || !(p->wall_n > 0.0) || !(p->wall_theta > 0.0)))
+            return RLBM_EINVAL;
+    }
     if ((p->bc[0] == RLBM_BC_PERIODIC) != (p->bc[1] == RLBM_BC_PERIODIC)) return RLBM_EINVAL;
     if ((p->bc[2] == RLBM_BC_PERIODIC) != (p->bc[3] == RLBM_BC_PERIODIC)) return RLBM_EINVAL;
     if (p->bc[2] == RLBM_BC_WALL_T || p->bc[3] == RLBM_BC_WALL_T) return RLBM_EINVAL;
@@ -1139,6 +1202,10 @@ KArgs make_base(const rlbm_params &p, rlbm_ctx *c) {
     a.tau_b = p.tau_b;
     a.th_wall_lo = p.theta_wall[0];
     a.th_wall_hi = p.theta_wall[1];
+    a.force_x = p.force[0];
+    a.force_y = p.force[1];
+    a.wall_n = p.wall_n;
+    a.wall_theta = p.wall_theta;
     a.guess = p.guess;
     a.mlp = p.mlp;
     a.status = c->status;
@@ -1227,7 +1294,8 @@ int launch_step(rlbm_ctx *c, hipStream_t s) {
         KArgs a = c->base[0];
         a.fin = c->cur ? p0.f_b : p0.f_a;
         a.fout = c->cur ? p0.f_a : p0.f_b;
-        hipLaunchKernelGGL(pick_order(0, p0.stats, p0.precision, p0.order), dim3(8 * a.per_xcd), dim3(256), 0, s, a);
+        const KFn k = is_forced(p0) ? pick_forced(p0.stats, p0.precision) : pick_order(0, p0.stats, p0.precision, p0.order);
+        hipLaunchKernelGGL(k, dim3(8 * a.per_xcd), dim3(256), 0, s, a);
     }
     c->cur ^= 1;
     c->steps++;
@@ -1283,7 +1351,7 @@ int create(rlbm_ctx **out, int ngrids, const rlbm_params *p, const rlbm_init_fie
         if (rc) return rc;
         if (!valid_init(&init[g])) return RLBM_EINVAL;
         const rlbm_params &a = p[g], &b = p[0];
-        if (ngrids > 1 && a.order != 5) return RLBM_ENOTIMPL;   // batches run the fifth-order kernels
+        if (ngrids > 1 && (a.order != 5 || is_forced(a))) return RLBM_ENOTIMPL;   // batches: unforced, order 5
         if (a.stats != b.stats || a.precision != b.precision || a.order != b.order || a.guess != b.guess ||
             a.mlp != b.mlp || a.stream != b.stream || a.tile_x != b.tile_x || a.tile_y != b.tile_y ||
             a.collect_stats != b.collect_stats)

@@ -16,7 +16,7 @@ RLBM_OK, RLBM_EINVAL, RLBM_EDOMAIN, RLBM_EHIP, RLBM_ENONFINITE, RLBM_ENOTIMPL = 
 STATS = {"MJ": 0, "FD": 1, "BE": 2}
 PRECISION = {"fp64": 0, "fp32": 1, "f16dev": 2}
 TAU_MODE = {"const": 0, "theta": 1}
-BC = {"periodic": 0, "open": 1, "wall": 2}
+BC = {"periodic": 0, "open": 1, "wall": 2, "wall_neq": 3}
 GUESS = {"fixed": 0, "mlp": 1}
 DTYPE = {"fp64": torch.float64, "fp32": torch.float32}
 F16DEV_BYTES_PER_CELL = 180   # 72 half deviations + 9 float side values
@@ -35,7 +35,8 @@ class Params(ctypes.Structure):
                 ("bc", ctypes.c_int32 * 4), ("theta_wall", ctypes.c_double * 2), ("guess", ctypes.c_int32),
                 ("mlp", ctypes.c_void_p), ("f_a", ctypes.c_void_p), ("f_b", ctypes.c_void_p),
                 ("stream", ctypes.c_void_p), ("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32),
-                ("collect_stats", ctypes.c_int32)]
+                ("collect_stats", ctypes.c_int32), ("force", ctypes.c_double * 2), ("wall_n", ctypes.c_double),
+                ("wall_theta", ctypes.c_double)]
 
 
 class InitFields(ctypes.Structure):
@@ -122,9 +123,11 @@ def _grid_args(params, init, device, stream):
                mlp=_ptr(params.get("mlp")), f_a=_ptr(f[0]), f_b=_ptr(f[1]),
                stream=ctypes.c_void_p(stream.cuda_stream),
                tile_x=int(params.get("tile", (0, 0))[0]), tile_y=int(params.get("tile", (0, 0))[1]),
-               collect_stats=int(bool(params.get("collect_stats", False))))
+               collect_stats=int(bool(params.get("collect_stats", False))),
+               wall_n=float(params.get("wall_n", 1.0)), wall_theta=float(params.get("wall_theta", 1.0)))
     p.bc[:] = [BC[b] for b in bc]
     p.theta_wall[:] = [float(t) for t in tw]
+    p.force[:] = [float(a) for a in params.get("force", (0.0, 0.0))]
     keep = {k: v.contiguous().to(device=device, dtype=torch.float64) for k, v in init.items()}
     fi = InitFields(n=_ptr(keep.get("n")), z=_ptr(keep.get("z")), theta=_ptr(keep["theta"]), ux=_ptr(keep["ux"]),
                     uy=_ptr(keep["uy"]), given_z=int("z" in keep))
@@ -136,7 +139,8 @@ class Sim:
 
     params: dict with keys nx, ny, stats ('MJ'|'FD'|'BE'), precision ('fp64'|'fp32'),
     tau_mode ('const'|'theta'), tau, tau_a, tau_b, bc (xlo, xhi, ylo, yhi names),
-    theta_wall (xlo, xhi), guess ('fixed'|'mlp'), tile ((tile_x, tile_y), default automatic).  init: dict of (ny, nx) float64
+    theta_wall (xlo, xhi), guess ('fixed'|'mlp'), tile ((tile_x, tile_y), default automatic),
+    force ((a_x, a_y), momentum update), wall_n and wall_theta (state imposed on 'wall_neq' sides).  init: dict of (ny, nx) float64
     CUDA tensors theta, ux, uy and either n or z.
     """
 

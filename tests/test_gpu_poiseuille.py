@@ -1,0 +1,151 @@
+"""Forced flow and non-equilibrium-extrapolation walls on the GPU (Sec. 3.4):
+parity with the FP64 oracle, then the Poiseuille grid-convergence study.
+
+Convergence reading: on this lattice the shear viscosity for
+wavevectors along an axis, which is what Poiseuille flow feels, is not the
+Taylor-Green value of Eq. nu-ref-eq (Taylor-Green modes have diagonal wavevectors and
+the interpolated streaming is anisotropic): at tau = 3 it is about 1.5% larger.  The
+error against the parabola built with Eq. nu-ref-eq therefore levels off near 1.5%;
+against the parabola built with the viscosity of a shear wave of the same
+orientation and resolution (measured on the GPU too) it keeps falling with a slope
+close to the paper's -2.037."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from conftest import read_golden
+from oracle import lattice as L
+
+pytestmark = pytest.mark.gpu
+
+GOLD = {k: float(v) for k, v in read_golden("poiseuille.txt")}
+FIELD_TOL_FP64 = dict(n=1e-12, eps=1e-12, theta=2e-12, z=5e-12)
+VEL_TOL_FP64 = 1e-12
+
+
+@pytest.fixture(scope="module")
+def rl():
+    from paper_1709_09073_amd import rlbm
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return rlbm
+
+
+def _oracle_params(params, stats):
+    bcs = dict(zip(("xlo", "xhi", "ylo", "yhi"), params["bc"]))
+    return L.Params(stats=stats, nx=params["nx"], ny=params["ny"], tau=params["tau"], bc=bcs,
+                    force=params.get("force", (0.0, 0.0)),
+                    wall_eq=dict(n=params.get("wall_n", 1.0), theta=params.get("wall_theta", 1.0)))
+
+
+@pytest.mark.parametrize("stats", ["MJ", "FD", "BE"])
+def test_forced_walls_parity_fp64(rl, stats):
+    nx, ny, steps = 12, 11, 6
+    params, _ = workloads.poiseuille(L=ny - 1, nx=nx, a=2e-3, tau=1.1)
+    params = dict(params, stats=stats, precision="fp64", wall_n=1.1, wall_theta=0.95)
+    fields = workloads.smooth_random(nx, ny, seed=13, stats=stats, amp_u=0.1)
+    print(f"[poiseuille] parity {stats} {nx}x{ny} {steps} steps", flush=True)
+    sim = rl.Sim(params, {k: v.cuda() for k, v in fields.items()})
+    sim.step(steps)
+    got = {k: v.cpu().numpy() for k, v in sim.fields().items()}
+    pops = sim.state().cpu().numpy()
+    sim.close()
+    op = _oracle_params(params, stats)
+    f0 = {k: v.numpy() for k, v in fields.items()}
+    f = L.run(L.init_state(op, f0["theta"], f0["ux"], f0["uy"], z=f0["z"]), op, steps)
+    ref = L.fields(f, op)
+    for k in range(6):
+        sl = slice(k, 72, 6)
+        err = np.abs(pops[sl] - f[sl]).max() / np.abs(f[sl]).max()
+        assert err <= (2e-12, 2e-12, 2e-12, 5e-12, 2e-11, 2e-10)[k], (k, err)
+    for key, tol in FIELD_TOL_FP64.items():
+        err = np.abs(got[key] - ref[key]).max() / np.abs(ref[key]).max()
+        print(f"  {key} err {err:.2e}")
+        assert err <= tol, (key, err)
+    for key in ("ux", "uy"):
+        err = np.abs(got[key] - ref[key]).max() / max(np.abs(ref[key]).max(), 0.01)
+        assert err <= VEL_TOL_FP64, (key, err)
+
+
+def test_forced_walls_parity_fp32(rl):
+    nx, ny, steps = 12, 11, 6
+    params, _ = workloads.poiseuille(L=ny - 1, nx=nx, a=2e-3, tau=1.1)
+    params = dict(params, stats="FD", precision="fp32")
+    fields = workloads.smooth_random(nx, ny, seed=14, stats="FD", amp_u=0.1)
+    sim = rl.Sim(params, {k: v.cuda() for k, v in fields.items()})
+    sim.step(steps)
+    got = {k: v.cpu().numpy() for k, v in sim.fields().items()}
+    sim.close()
+    op = _oracle_params(params, "FD")
+    f0 = {k: v.numpy() for k, v in fields.items()}
+    ref = L.fields(L.run(L.init_state(op, f0["theta"], f0["ux"], f0["uy"], z=f0["z"]), op, steps), op)
+    for key, tol in dict(n=2e-6, eps=2e-6, theta=2e-6, z=5e-6).items():
+        assert np.abs(got[key] - ref[key]).max() / np.abs(ref[key]).max() <= tol, key
+    for key in ("ux", "uy"):
+        assert np.abs(got[key] - ref[key]).max() / max(np.abs(ref[key]).max(), 0.01) <= 2e-5, key
+
+
+def _poiseuille_profile(rl, L_, tau, a):
+    params, fields = workloads.poiseuille(L=L_, a=a, tau=tau)
+    nu = (tau - 0.2546) / 4
+    steps = int(math.ceil(30 * L_ * L_ / (math.pi ** 2 * nu)))
+    sim = rl.Sim(dict(params, precision="fp64"), {k: v.cuda() for k, v in fields.items()})
+    sim.capture()
+    sim.step(steps)
+    u = sim.fields()["ux"][:, 0].cpu().numpy()
+    sim.close()
+    return u, steps
+
+
+def _shear_nu(rl, L_, tau):
+    params, fields = workloads.shear_wave(L=L_, tau=tau)
+    nu0 = (tau - 0.2546) / 4
+    k2 = (2 * math.pi / L_) ** 2
+    total = int(2 / (nu0 * k2))
+    chunk = max(1, total // 20)
+    sim = rl.Sim(dict(params, precision="fp64"), {k: v.cuda() for k, v in fields.items()})
+    sim.capture()
+    ts, amp = [], []
+    t = 0
+    while t <= total:
+        if t > total // 5:
+            u = sim.fields()["ux"][:, 0].cpu().numpy()
+            ts.append(t)
+            amp.append(np.sqrt(np.mean(u * u)))
+        sim.step(chunk)
+        t += chunk
+    sim.close()
+    return -np.polyfit(ts, np.log(amp), 1)[0] / k2
+
+
+def test_poiseuille_grid_convergence(rl):
+    tau, a = GOLD["tau"], GOLD["accel"]
+    nu_formula = (tau - 0.2546) / 4
+    assert abs(nu_formula - GOLD["nu"]) < 1e-4
+    sizes = (8, 16, 32, 64, 128, 256)
+    e_formula, e_shear = [], []
+    for L_ in sizes:
+        u, steps = _poiseuille_profile(rl, L_, tau, a)
+        nu_s = _shear_nu(rl, L_, tau)
+        y = np.arange(L_ + 1)
+        ref_f = a / (2 * nu_formula) * y * (L_ - y)
+        ref_s = a / (2 * nu_s) * y * (L_ - y)
+        ef = np.sqrt(np.sum((u - ref_f) ** 2) / np.sum(ref_f ** 2))
+        es = np.sqrt(np.sum((u - ref_s) ** 2) / np.sum(ref_s ** 2))
+        e_formula.append(ef)
+        e_shear.append(es)
+        print(f"  L={L_:4d} steps={steps:7d} nu_shear={nu_s:.5f} (formula {nu_formula:.5f}) "
+              f"eps_u: formula-nu {ef:.3e}, shear-nu {es:.3e}", flush=True)
+        assert np.abs(u - u[::-1]).max() <= 1e-6 * np.abs(u).max()
+    lx = np.log(sizes)
+    slope_s = np.polyfit(lx, np.log(e_shear), 1)[0]
+    slope_f = np.polyfit(lx, np.log(e_formula), 1)[0]
+    print(f"  slope with the shear-wave nu {slope_s:.3f}, with Eq. nu-ref-eq {slope_f:.3f} "
+          f"(paper {GOLD['slope']})")
+    assert -2.6 < slope_s < -1.6
+    assert all(e_shear[i + 1] < e_shear[i] for i in range(len(sizes) - 1))
+    # against Eq. nu-ref-eq the error levels off at the viscosity mismatch
+    assert 0.005 < e_formula[-1] < 0.03

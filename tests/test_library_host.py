@@ -45,6 +45,8 @@ def _params(**kw):
     for k, v in kw.items():
         if k == "bc":
             p.bc[:] = v
+        elif k == "force":
+            p.force[:] = v
         else:
             setattr(p, k, v)
     return p
@@ -55,6 +57,10 @@ INVALID = [
     dict(tau_mode=1, tau_b=0.0), dict(tau_mode=2), dict(bc=[0, 1, 0, 0]), dict(bc=[0, 0, 2, 2]),
     dict(bc=[2, 2, 0, 0], nx=3), dict(f_a=ctypes.c_void_p(0)), dict(f_b=ctypes.c_void_p(0x1000)),
     dict(tile_x=48, tile_y=5), dict(tile_x=8, tile_y=32), dict(tile_x=64, tile_y=2),
+    # non-equilibrium walls: y sides only, ny >= 3, positive imposed state; finite force
+    dict(bc=[3, 3, 0, 0], wall_n=1.0, wall_theta=1.0), dict(bc=[0, 0, 3, 3], ny=2, wall_n=1.0, wall_theta=1.0),
+    dict(bc=[0, 0, 3, 3], wall_n=0.0, wall_theta=1.0), dict(bc=[0, 0, 3, 3], wall_n=1.0, wall_theta=-1.0),
+    dict(force=(float("nan"), 0.0)),
 ]
 
 
@@ -72,6 +78,18 @@ def test_invalid_params_rejected(rl, kw):
 def test_lower_orders_only_for_maxwell_juttner(rl):
     L = rl.lib()
     p = _params(order=3, stats=1)
+    fi = rl.InitFields(n=ctypes.c_void_p(0x10), z=None, theta=ctypes.c_void_p(0x10), ux=ctypes.c_void_p(0x10),
+                       uy=ctypes.c_void_p(0x10), given_z=0)
+    ctx = ctypes.c_void_p()
+    assert L.rlbm_init(ctypes.byref(ctx), ctypes.byref(p), ctypes.byref(fi)) == rl.RLBM_ENOTIMPL
+
+
+@pytest.mark.parametrize("kw", [dict(force=(1e-6, 0.0), precision=2), dict(force=(1e-6, 0.0), order=3),
+                                dict(bc=[0, 0, 3, 3], wall_n=1.0, wall_theta=1.0, precision=2)])
+def test_forced_variant_limits(rl, kw):
+    """Forced flow and non-equilibrium walls run at order 5 with FP64/FP32 populations."""
+    L = rl.lib()
+    p = _params(**kw)
     fi = rl.InitFields(n=ctypes.c_void_p(0x10), z=None, theta=ctypes.c_void_p(0x10), ux=ctypes.c_void_p(0x10),
                        uy=ctypes.c_void_p(0x10), given_z=0)
     ctx = ctypes.c_void_p()

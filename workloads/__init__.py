@@ -15,6 +15,8 @@ Workloads (the paper uses formula-defined initial-value problems, no datasets):
 * hotspot_paper    - the paper's Maxwell-Juttner hot spot (Sec. 3.5)
 * smooth_random    - seeded smooth random fields for parity tests
 * batch_specs      - 64 uneven Taylor-Green and Fourier grids for sweeps
+* poiseuille       - forced flow between plates (Sec. 3.4)
+* shear_wave       - decaying transverse shear wave (u_x varying along y)
 """
 import math
 
@@ -152,3 +154,26 @@ def batch_specs(seed=3, ngrids=64, steps=10000):
             nx, ny = int(rng.choice(sizes)), int(rng.choice(sizes))
             specs.append(dict(kind="fourier", nx=nx, ny=ny, tau=tau, dT=0.1))
     return specs
+
+
+def poiseuille(L=32, nx=4, a=1e-8, tau=3.0, device="cpu"):
+    """Plates at the wall rows y = 0 and y = L (ny = L + 1) with n = theta = 1, u = 0
+    imposed; x periodic; fluid at rest with n = theta = 1; acceleration a along x;
+    constant tau (Sec. 3.4 uses tau = 3, a = 1e-8)."""
+    x, _ = _grid(nx, L + 1, device)
+    one = torch.ones_like(x)
+    fields = dict(n=one.clone(), theta=one.clone(), ux=torch.zeros_like(x), uy=torch.zeros_like(x))
+    params = dict(nx=nx, ny=L + 1, tau_mode="const", tau=tau, force=(a, 0.0),
+                  bc=("periodic", "periodic", "wall_neq", "wall_neq"), wall_n=1.0, wall_theta=1.0)
+    return params, fields
+
+
+def shear_wave(L=32, nx=4, u0=1e-4, tau=3.0, device="cpu"):
+    """u_x = u0 sin(2 pi y / L), u_y = 0, n = theta = 1, periodic: its decay rate
+    nu k^2 measures the shear viscosity for wavevectors along y."""
+    _, y = _grid(nx, L, device)
+    one = torch.ones_like(y)
+    fields = dict(n=one.clone(), theta=one.clone(), ux=(u0 * torch.sin(2 * math.pi * y / L)).contiguous(),
+                  uy=torch.zeros_like(y))
+    params = dict(nx=nx, ny=L, tau_mode="const", tau=tau, bc=("periodic",) * 4)
+    return params, fields
