@@ -906,6 +906,25 @@ __global__ RLBM_BATCH_BOUNDS(ST, R) void k_step_batch(Batch b, const KArgs *__re
     }
 }
 
+// One workgroup per tile of the batch (workgroup b takes tile (b % 8) per_xcd + b / 8,
+// so each XCD sweeps a contiguous range).  Without the persistent loop the kernel
+// fits the single-grid register budget (3 waves per SIMD for FP32).
+template <int ST, typename S, typename R>
+__global__ RLBM_STEP_BOUNDS(ST, R, false) void k_step_tiles(Batch b, const KArgs *__restrict__ descs,
+                                                        const int *__restrict__ tile_grid,
+                                                        const int *__restrict__ tile_base) {
+    const int t = (blockIdx.x & 7) * b.per_xcd + (blockIdx.x >> 3);
+    if (t >= b.ntiles) return;
+    const int g = __builtin_amdgcn_readfirstlane(tile_grid[t]);
+    const KArgs a = descs[g];
+    const int lt = t - __builtin_amdgcn_readfirstlane(tile_base[g]);
+    const int tyi = lt / a.ntx;
+    const int txi = lt - tyi * a.ntx;
+    const int x = txi * a.tx + (int)threadIdx.x % a.tx;
+    const int y = tyi * a.ty + (int)threadIdx.x / a.tx;
+    if (x < a.nx && y < a.ny) step_cell<ST, S, R>(a, x, y);
+}
+
 template <int ST, typename S, typename R>
 __global__ __launch_bounds__(256) void k_moments(KArgs a) {
     int x, y;
@@ -1029,6 +1048,10 @@ struct Kern {
         return prec == RLBM_FP64 ? k_step_batch<ST, double, double>
              : prec == RLBM_FP32 ? k_step_batch<ST, float, float> : k_step_batch<ST, Dev16, float>;
     }
+    static BFn tiles(int prec) {
+        return prec == RLBM_FP64 ? k_step_tiles<ST, double, double>
+             : prec == RLBM_FP32 ? k_step_tiles<ST, float, float> : k_step_tiles<ST, Dev16, float>;
+    }
     static KFn mom(int prec) {
         return prec == RLBM_FP64 ? k_moments<ST, double, double>
              : prec == RLBM_FP32 ? k_moments<ST, float, float> : k_moments<ST, Dev16, float>;
@@ -1080,7 +1103,9 @@ KFn pick_noneq(int st, int prec, int order) {
          : order == 4 ? noneq_kernel<RLBM_MJ, 4>(prec) : noneq_kernel<RLBM_MJ, 5>(prec);
 }
 
-BFn pick_batch(int st, int prec) {
+BFn pick_batch(int st, int prec, bool persistent) {
+    if (!persistent)
+        return st == RLBM_MJ ? Kern<RLBM_MJ>::tiles(prec) : st == RLBM_FD ? Kern<RLBM_FD>::tiles(prec) : Kern<RLBM_BE>::tiles(prec);
     return st == RLBM_MJ ? Kern<RLBM_MJ>::batch(prec) : st == RLBM_FD ? Kern<RLBM_FD>::batch(prec) : Kern<RLBM_BE>::batch(prec);
 }
 
@@ -1288,8 +1313,9 @@ int launch_step(rlbm_ctx *c, hipStream_t s) {
         b.per_xcd = (c->ntiles_total + 7) / 8;
         b.groups_per_xcd = c->batch_groups_per_xcd;
         const KArgs *descs = c->d_descs + (size_t)c->cur * c->base.size();
-        hipLaunchKernelGGL(pick_batch(p0.stats, p0.precision), dim3(8 * b.groups_per_xcd), dim3(256), 0, s, b, descs,
-                           (const int *)c->d_tile_grid, (const int *)c->d_tile_base);
+        const bool persistent = b.groups_per_xcd < b.per_xcd;
+        hipLaunchKernelGGL(pick_batch(p0.stats, p0.precision, persistent), dim3(8 * b.groups_per_xcd), dim3(256), 0, s, b,
+                           descs, (const int *)c->d_tile_grid, (const int *)c->d_tile_base);
     } else {
         KArgs a = c->base[0];
         a.fin = c->cur ? p0.f_b : p0.f_a;
