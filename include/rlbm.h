@@ -62,9 +62,10 @@ enum rlbm_stats { RLBM_MJ = 0, RLBM_FD = 1, RLBM_BE = 2 };         /* Eqs. mj-w-
 /* Population storage.  RLBM_F16DEV (project extension): per cell the deviations
  * e_i = (f_i / w_k - R_i) / s as IEEE half, R_{k,n} = rho_k + p_k (alpha cos phi_n
  * + beta sin phi_n) (direction average of f/w per shell plus a least-squares
- * p-weighted dipole), s = max_i |f_i / w_k - R_i|; a buffer holds 72 half planes
- * (q = 6 n + k) followed by 9 float planes rho_0..rho_5, alpha, beta, s: 180 bytes
- * per cell.  Arithmetic as RLBM_FP32. */
+ * p-weighted dipole), s = max_i |f_i / w_k - R_i|.  A buffer holds 12 direction
+ * blocks, each nx*ny cells (y-major, x fastest) of 6 halves (shells k = 0..5, 12
+ * bytes), then nx*ny cells of 9 floats rho_0..rho_5, alpha, beta, s (36 bytes): 180
+ * bytes per cell.  Arithmetic as RLBM_FP32. */
 enum rlbm_precision { RLBM_FP64 = 0, RLBM_FP32 = 1, RLBM_F16DEV = 2 };
 enum rlbm_tau_mode { RLBM_TAU_CONST = 0, RLBM_TAU_INV_THETA = 1 };  /* tau, or tau_a/theta + tau_b */
 enum rlbm_bc {

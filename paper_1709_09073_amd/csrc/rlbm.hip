@@ -649,31 +649,51 @@ __device__ __forceinline__ void store(S *__restrict__ fout, long long plane, int
 // Per cell: e_i = (f_i / w_k - R_i) / s stored as IEEE half, with the reference
 // R_{k,n} = rho_k + p_k (alpha cos phi_n + beta sin phi_n) (the direction average of
 // f/w per shell plus one p-weighted dipole, least squares) and the scale
-// s = max_i |f_i / w_k - R_i|.  Buffer layout: 72 half planes (q = 6 n + k), then 9
-// float planes rho_0..rho_5, alpha, beta, s.  The reference is linear in the side
-// values, so a pull interpolates the side values with the bilinear weights and the
-// deviations with the weights times the source scales.
+// s = max_i |f_i / w_k - R_i|.  Buffer layout (180 bytes per cell): 12 direction
+// blocks of nx*ny cells x 6 halves (12 bytes per cell, shells k = 0..5 in order),
+// then nx*ny cells x 9 floats rho_0..rho_5, alpha, beta, s (36 bytes per cell).  A
+// direction's six deviations of a cell are one 12-byte load; a cell's side values
+// three.  The reference is linear in the side values, so a pull interpolates the side
+// values with the bilinear weights and the deviations with the weights times the
+// source scales.
 struct Dev16 {};
 
-__device__ __forceinline__ float half_bits_to_float(unsigned short h) {
-    return (float)__builtin_bit_cast(_Float16, h);
+typedef unsigned int u32x3 __attribute__((ext_vector_type(3)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+
+// Vector elements are copied to scalars before a bit cast: clang takes
+// __builtin_bit_cast of an ext_vector element as a cast of element 0.
+__device__ __forceinline__ float u32_as_float(unsigned u) { return __builtin_bit_cast(float, u); }
+
+// half k (0..5) of a cell's packed deviations
+__device__ __forceinline__ float dev_half(const u32x3 &v, int k) {
+    const unsigned u = v[k >> 1];
+    const f16x2 h = __builtin_bit_cast(f16x2, u);
+    return (float)((k & 1) ? h.y : h.x);
 }
 
 struct SideRef {
     float v[9];   // rho_0..rho_5, alpha, beta, s
 };
 
-__device__ __forceinline__ void load_side(rsrc_t rs, unsigned cell, unsigned pb4, SideRef &o) {
+__device__ __forceinline__ void load_side(rsrc_t rs, unsigned cell, SideRef &o) {
 #pragma unroll
-    for (int j = 0; j < 9; ++j) o.v[j] = bload<float>(rs, cell * 4u, (unsigned)j * pb4);
+    for (int j = 0; j < 3; ++j) {
+        const u32x3 w = __builtin_amdgcn_raw_buffer_load_b96(rs, cell * 36u, (unsigned)j * 12u, LOAD_POLICY);
+        o.v[3 * j] = u32_as_float(w[0]);
+        o.v[3 * j + 1] = u32_as_float(w[1]);
+        o.v[3 * j + 2] = u32_as_float(w[2]);
+    }
 }
 
-// One direction n with taps (cell offset, weight, side values).
+// One direction n with taps (cell index, weight, side values).
 template <int ST, int N, int NT>
 __device__ __forceinline__ void dev_direction(const char *base, long long plane, const unsigned (&cell)[NT],
                                               const float (&wt)[NT], const SideRef *const (&sd)[NT], float (&f)[72]) {
-    const unsigned pb2 = (unsigned)plane * 2u;
-    const rsrc_t r = make_rsrc(base + (long long)(6 * N) * plane * 2, 6u * pb2);
+    const rsrc_t r = make_rsrc(base + (long long)N * plane * 12, 12u * (unsigned)plane);
+    u32x3 d[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) d[t] = __builtin_amdgcn_raw_buffer_load_b96(r, cell[t] * 12u, 0u, LOAD_POLICY);
     float rb[6], ab = 0.0f, bb = 0.0f, ws[NT];
 #pragma unroll
     for (int k = 0; k < 6; ++k) rb[k] = 0.0f;
@@ -690,11 +710,7 @@ __device__ __forceinline__ void dev_direction(const char *base, long long plane,
     for (int k = 0; k < 6; ++k) {
         float acc = rb[k] + (float)P_SHELL[ST][k] * tn;
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            const unsigned short h =
-                __builtin_amdgcn_raw_buffer_load_b16(r, cell[t] * 2u, (unsigned)k * pb2, LOAD_POLICY);
-            acc += ws[t] * half_bits_to_float(h);
-        }
+        for (int t = 0; t < NT; ++t) acc += ws[t] * dev_half(d[t], k);
         f[6 * N + k] = (float)W_SHELL[ST][k] * acc;
     }
 }
@@ -703,37 +719,36 @@ template <int ST>
 __device__ __forceinline__ void pull_dev(const void *fin, long long plane, int nx, int x, int y, int xl, int xr, int yd,
                                          int yu, float (&f)[72]) {
     const char *base = (const char *)fin;
-    const unsigned pb4 = (unsigned)plane * 4u;
-    const rsrc_t rs = make_rsrc(base + 144LL * plane, 9u * pb4);
+    const rsrc_t rs = make_rsrc(base + 144LL * plane, 36u * (unsigned)plane);
     const unsigned cc = y * nx + x, cl = y * nx + xl, cr = y * nx + xr;
     const unsigned dc = yd * nx + x, dl = yd * nx + xl, dr = yd * nx + xr;
     const unsigned uc = yu * nx + x, ul = yu * nx + xl, ur = yu * nx + xr;
     const float wA = (float)(S3H * 0.5), wB = (float)((1.0 - S3H) * 0.5);
     SideRef C, A, B, D;
-    load_side(rs, cc, pb4, C);
+    load_side(rs, cc, C);
     // quadrant towards -x, -y: directions 0, 3 (axis), 1, 2
-    load_side(rs, cl, pb4, A);
-    load_side(rs, dc, pb4, B);
-    load_side(rs, dl, pb4, D);
+    load_side(rs, cl, A);
+    load_side(rs, dc, B);
+    load_side(rs, dl, D);
     dev_direction<ST, 0, 1>(base, plane, {cl}, {1.0f}, {&A}, f);
     dev_direction<ST, 3, 1>(base, plane, {dc}, {1.0f}, {&B}, f);
     dev_direction<ST, 1, 4>(base, plane, {dl, cl, dc, cc}, {wA, wA, wB, wB}, {&D, &A, &B, &C}, f);
     dev_direction<ST, 2, 4>(base, plane, {dl, dc, cl, cc}, {wA, wA, wB, wB}, {&D, &B, &A, &C}, f);
     // quadrant towards +x, -y: directions 6 (axis), 4, 5 (reuse the -y cell)
-    load_side(rs, cr, pb4, A);
-    load_side(rs, dr, pb4, D);
+    load_side(rs, cr, A);
+    load_side(rs, dr, D);
     dev_direction<ST, 6, 1>(base, plane, {cr}, {1.0f}, {&A}, f);
     dev_direction<ST, 4, 4>(base, plane, {dr, dc, cr, cc}, {wA, wA, wB, wB}, {&D, &B, &A, &C}, f);
     dev_direction<ST, 5, 4>(base, plane, {dr, cr, dc, cc}, {wA, wA, wB, wB}, {&D, &A, &B, &C}, f);
     // quadrant towards +x, +y: directions 9 (axis), 7, 8 (reuse the +x cell)
-    load_side(rs, uc, pb4, B);
-    load_side(rs, ur, pb4, D);
+    load_side(rs, uc, B);
+    load_side(rs, ur, D);
     dev_direction<ST, 9, 1>(base, plane, {uc}, {1.0f}, {&B}, f);
     dev_direction<ST, 7, 4>(base, plane, {ur, cr, uc, cc}, {wA, wA, wB, wB}, {&D, &A, &B, &C}, f);
     dev_direction<ST, 8, 4>(base, plane, {ur, uc, cr, cc}, {wA, wA, wB, wB}, {&D, &B, &A, &C}, f);
     // quadrant towards -x, +y: directions 10, 11 (reuse the +y cell)
-    load_side(rs, cl, pb4, A);
-    load_side(rs, ul, pb4, D);
+    load_side(rs, cl, A);
+    load_side(rs, ul, D);
     dev_direction<ST, 10, 4>(base, plane, {ul, uc, cl, cc}, {wA, wA, wB, wB}, {&D, &B, &A, &C}, f);
     dev_direction<ST, 11, 4>(base, plane, {ul, cl, uc, cc}, {wA, wA, wB, wB}, {&D, &A, &B, &C}, f);
 }
@@ -741,7 +756,6 @@ __device__ __forceinline__ void pull_dev(const void *fin, long long plane, int n
 template <int ST>
 __device__ __forceinline__ void store_dev(void *fout, long long plane, int off, const float (&f)[72]) {
     char *base = (char *)fout;
-    const unsigned pb2 = (unsigned)plane * 2u, pb4 = (unsigned)plane * 4u;
     float g[72];
 #pragma unroll
     for (int q = 0; q < 72; ++q) g[q] = f[q] * (float)(1.0 / W_SHELL[ST][q % 6]);
@@ -775,22 +789,26 @@ __device__ __forceinline__ void store_dev(void *fout, long long plane, int off, 
         }
     }
     const float inv = smax > 0.0f ? 1.0f / smax : 0.0f;
+    const unsigned uoff = (unsigned)off;
 #pragma unroll
     for (int n = 0; n < 12; ++n) {
-        const rsrc_t r = make_rsrc(base + (long long)(6 * n) * plane * 2, 6u * pb2);
+        const rsrc_t r = make_rsrc(base + (long long)n * plane * 12, 12u * (unsigned)plane);
+        u32x3 w;
 #pragma unroll
-        for (int k = 0; k < 6; ++k) {
-            const _Float16 h = (_Float16)(g[6 * n + k] * inv);
-            __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, h), r, (unsigned)off * 2u,
-                                                  (unsigned)k * pb2, STORE_POLICY);
+        for (int j = 0; j < 3; ++j) {
+            const f16x2 h = {(_Float16)(g[6 * n + 2 * j] * inv), (_Float16)(g[6 * n + 2 * j + 1] * inv)};
+            w[j] = __builtin_bit_cast(unsigned, h);
         }
+        __builtin_amdgcn_raw_buffer_store_b96(w, r, uoff * 12u, 0u, STORE_POLICY);
     }
-    const rsrc_t rs = make_rsrc(base + 144LL * plane, 9u * pb4);
+    const rsrc_t rs = make_rsrc(base + 144LL * plane, 36u * (unsigned)plane);
+    const float sv[9] = {rho[0], rho[1], rho[2], rho[3], rho[4], rho[5], alpha, beta, smax};
 #pragma unroll
-    for (int k = 0; k < 6; ++k) bstore<float>(rho[k], rs, (unsigned)off * 4u, (unsigned)k * pb4);
-    bstore<float>(alpha, rs, (unsigned)off * 4u, 6u * pb4);
-    bstore<float>(beta, rs, (unsigned)off * 4u, 7u * pb4);
-    bstore<float>(smax, rs, (unsigned)off * 4u, 8u * pb4);
+    for (int j = 0; j < 3; ++j) {
+        const u32x3 w = {__builtin_bit_cast(unsigned, sv[3 * j]), __builtin_bit_cast(unsigned, sv[3 * j + 1]),
+                         __builtin_bit_cast(unsigned, sv[3 * j + 2])};
+        __builtin_amdgcn_raw_buffer_store_b96(w, rs, uoff * 36u, (unsigned)j * 12u, STORE_POLICY);
+    }
 }
 
 __device__ __forceinline__ void report(unsigned *status, unsigned flags) {

@@ -230,11 +230,13 @@ class Sim:
 
 
 def f16dev_views(buf, nx, ny):
-    """(deviation planes (72, ny, nx) float16, side planes (9, ny, nx) float32) of an
-    RLBM_F16DEV buffer (views, no copy)."""
+    """(deviations (72, ny, nx) float16 with q = 6 n + k, side values (9, ny, nx)
+    float32) of an RLBM_F16DEV buffer, rearranged from its cell-packed layout
+    (12 direction blocks of cells x 6 halves, then cells x 9 floats); copies."""
     raw = buf.view(torch.uint8)
-    dev = raw[: 144 * nx * ny].view(torch.float16).view(72, ny, nx)
-    side = raw[144 * nx * ny: 180 * nx * ny].view(torch.float32).view(9, ny, nx)
+    P = nx * ny
+    dev = raw[: 144 * P].view(torch.float16).view(12, ny, nx, 6).permute(0, 3, 1, 2).reshape(72, ny, nx)
+    side = raw[144 * P: 180 * P].view(torch.float32).view(ny, nx, 9).permute(2, 0, 1).contiguous()
     return dev, side
 
 
