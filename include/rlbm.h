@@ -13,10 +13,12 @@
  * density-eq, theta-eq, n-eps-eq, heat-eq2).
  *
  * Conventions
- *  - Populations: structure of arrays f[q][y][x], q = 6*n + k with direction
- *    n = 0..11 (angle n*pi/6; the paper's label i = n + 1) and radial shell
- *    k = 0..5; cell (x, y) at integer coordinates, x fastest.  The element type
- *    is double (RLBM_FP64) or float (RLBM_FP32): 72*nx*ny elements per buffer;
+ *  - Populations f_q, q = 6*n + k with direction n = 0..11 (angle n*pi/6; the
+ *    paper's label i = n + 1) and radial shell k = 0..5; cell c = y*nx + x at
+ *    integer coordinates (x, y).  A buffer holds 12 direction blocks of P = nx*ny
+ *    cells; inside block n the six shells of a cell form 16-byte records: FP32
+ *    (float) shells 0..3 at byte 16*c, shells 4..5 at 16*P + 8*c; FP64 (double)
+ *    shells 2j, 2j+1 at 16*j*P + 16*c (j = 0, 1, 2).  72*nx*ny elements per buffer.
  *    RLBM_F16DEV buffers hold 180*nx*ny bytes (layout at enum rlbm_precision).
  *  - The stored state is the post-collision population.  One step is: pull
  *    streaming, moments N^mu and T^{mu nu}, Landau frame (Eq. eigen-eq), density

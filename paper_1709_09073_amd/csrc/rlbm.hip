@@ -169,6 +169,68 @@ __device__ __forceinline__ void bstore<double>(double v, rsrc_t r, unsigned voff
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u, v), r, voff, soff, STORE_POLICY);
 }
 
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x3 __attribute__((ext_vector_type(3)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+
+// Vector elements are copied to scalars before a bit cast: clang takes
+// __builtin_bit_cast of an ext_vector element as a cast of element 0.
+__device__ __forceinline__ float u32_as_float(unsigned u) { return __builtin_bit_cast(float, u); }
+__device__ __forceinline__ unsigned float_as_u32(float v) { return __builtin_bit_cast(unsigned, v); }
+__device__ __forceinline__ double u32_as_double(unsigned lo, unsigned hi) {
+    return __builtin_bit_cast(double, (unsigned long long)lo | ((unsigned long long)hi << 32));
+}
+
+// A direction block of FP32/FP64 populations holds, per cell, the six shells as
+// 16-byte records: FP32 shells 0..3 (record at cell*16) then shells 4..5 (8 bytes at
+// 16*P + cell*8); FP64 shells 2j, 2j+1 at 16*j*P + cell*16, j = 0, 1, 2 (P = nx*ny).
+template <typename S>
+struct Rec;
+
+template <>
+struct Rec<float> {
+    static __device__ __forceinline__ void load(rsrc_t r, unsigned cell, unsigned P, float (&v)[6]) {
+        const u32x4 a = __builtin_amdgcn_raw_buffer_load_b128(r, cell * 16u, 0u, LOAD_POLICY);
+        const u32x2 b = __builtin_amdgcn_raw_buffer_load_b64(r, cell * 8u, 16u * P, LOAD_POLICY);
+        unsigned e0 = a[0], e1 = a[1], e2 = a[2], e3 = a[3], e4 = b[0], e5 = b[1];
+        v[0] = u32_as_float(e0);
+        v[1] = u32_as_float(e1);
+        v[2] = u32_as_float(e2);
+        v[3] = u32_as_float(e3);
+        v[4] = u32_as_float(e4);
+        v[5] = u32_as_float(e5);
+    }
+    static __device__ __forceinline__ void store(rsrc_t r, unsigned cell, unsigned P, const float (&v)[6]) {
+        const u32x4 a = {float_as_u32(v[0]), float_as_u32(v[1]), float_as_u32(v[2]), float_as_u32(v[3])};
+        const u32x2 b = {float_as_u32(v[4]), float_as_u32(v[5])};
+        __builtin_amdgcn_raw_buffer_store_b128(a, r, cell * 16u, 0u, STORE_POLICY);
+        __builtin_amdgcn_raw_buffer_store_b64(b, r, cell * 8u, 16u * P, STORE_POLICY);
+    }
+};
+
+template <>
+struct Rec<double> {
+    static __device__ __forceinline__ void load(rsrc_t r, unsigned cell, unsigned P, double (&v)[6]) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const u32x4 a = __builtin_amdgcn_raw_buffer_load_b128(r, cell * 16u, 16u * (unsigned)j * P, LOAD_POLICY);
+            unsigned e0 = a[0], e1 = a[1], e2 = a[2], e3 = a[3];
+            v[2 * j] = u32_as_double(e0, e1);
+            v[2 * j + 1] = u32_as_double(e2, e3);
+        }
+    }
+    static __device__ __forceinline__ void store(rsrc_t r, unsigned cell, unsigned P, const double (&v)[6]) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const unsigned long long x = __builtin_bit_cast(unsigned long long, v[2 * j]);
+            const unsigned long long y = __builtin_bit_cast(unsigned long long, v[2 * j + 1]);
+            const u32x4 a = {(unsigned)x, (unsigned)(x >> 32), (unsigned)y, (unsigned)(y >> 32)};
+            __builtin_amdgcn_raw_buffer_store_b128(a, r, cell * 16u, 16u * (unsigned)j * P, STORE_POLICY);
+        }
+    }
+};
+
 // ---------------------------------------------------------------- streaming
 // Pull of all 72 populations of cell (x, y).  Axis directions shift by one cell;
 // the others interpolate bilinearly from (x, y), (xb, y), (x, yb), (xb, yb) with
@@ -178,32 +240,34 @@ __device__ __forceinline__ void bstore<double>(double v, rsrc_t r, unsigned voff
 template <typename S, typename R>
 __device__ __forceinline__ void pull(const S *__restrict__ fin, long long plane, int nx, int x, int y, int xl,
                                      int xr, int yd, int yu, R (&f)[72]) {
-    constexpr unsigned E = sizeof(S);
     const unsigned oc = (unsigned)(y * nx), od = (unsigned)(yd * nx), ou = (unsigned)(yu * nx);
-    const unsigned pb = (unsigned)plane * E;
+    const unsigned P = (unsigned)plane;
     const R wA = (R)(S3H * 0.5);
     const R wB = (R)((1.0 - S3H) * 0.5);
 #pragma unroll
     for (int n = 0; n < 12; ++n) {
-        const rsrc_t r = make_rsrc(fin + (long long)(6 * n) * plane, 6u * pb);
+        const rsrc_t r = make_rsrc(fin + (long long)(6 * n) * plane, 6u * P * (unsigned)sizeof(S));
         const unsigned xb = cdir(n) > 0.1 ? xl : xr;     // source column x - sgn(v_x)
         const unsigned rb = sdir(n) > 0.1 ? od : ou;     // source row    y - sgn(v_y)
-        const unsigned t_bb = (rb + xb) * E, t_bx = (rb + x) * E, t_cb = (oc + xb) * E, t_cx = (oc + x) * E;
+        if (n % 3 == 0) {
+            const unsigned src = n == 0 ? oc + xl : n == 3 ? od + x : n == 6 ? oc + xr : ou + x;
+            S v[6];
+            Rec<S>::load(r, src, P, v);
 #pragma unroll
-        for (int s = 0; s < 6; ++s) {
-            const unsigned so = (unsigned)s * pb;
-            R v;
-            if (n == 0) v = (R)bload<S>(r, (oc + xl) * E, so);
-            else if (n == 3) v = (R)bload<S>(r, (od + x) * E, so);
-            else if (n == 6) v = (R)bload<S>(r, (oc + xr) * E, so);
-            else if (n == 9) v = (R)bload<S>(r, (ou + x) * E, so);
-            else if (n == 1 || n == 5 || n == 7 || n == 11)   // |v_x| = sqrt3/2, |v_y| = 1/2
-                v = wA * ((R)bload<S>(r, t_bb, so) + (R)bload<S>(r, t_cb, so)) +
-                    wB * ((R)bload<S>(r, t_bx, so) + (R)bload<S>(r, t_cx, so));
-            else                                              // |v_x| = 1/2, |v_y| = sqrt3/2
-                v = wA * ((R)bload<S>(r, t_bb, so) + (R)bload<S>(r, t_bx, so)) +
-                    wB * ((R)bload<S>(r, t_cb, so) + (R)bload<S>(r, t_cx, so));
-            f[6 * n + s] = v;
+            for (int s = 0; s < 6; ++s) f[6 * n + s] = (R)v[s];
+        } else {
+            S bb[6], bx[6], cb[6], cx[6];
+            Rec<S>::load(r, rb + xb, P, bb);
+            Rec<S>::load(r, rb + x, P, bx);
+            Rec<S>::load(r, oc + xb, P, cb);
+            Rec<S>::load(r, oc + x, P, cx);
+#pragma unroll
+            for (int s = 0; s < 6; ++s) {
+                if (n == 1 || n == 5 || n == 7 || n == 11)   // |v_x| = sqrt3/2, |v_y| = 1/2
+                    f[6 * n + s] = wA * ((R)bb[s] + (R)cb[s]) + wB * ((R)bx[s] + (R)cx[s]);
+                else                                          // |v_x| = 1/2, |v_y| = sqrt3/2
+                    f[6 * n + s] = wA * ((R)bb[s] + (R)bx[s]) + wB * ((R)cb[s] + (R)cx[s]);
+            }
         }
     }
 }
@@ -634,14 +698,14 @@ __device__ __forceinline__ void equilibrium_relax(const Macro &M, double tau, R 
 
 template <typename S, typename R>
 __device__ __forceinline__ void store(S *__restrict__ fout, long long plane, int off, const R (&f)[72]) {
-    constexpr unsigned E = sizeof(S);
-    const unsigned pb = (unsigned)plane * E;
-    const unsigned vo = (unsigned)off * E;
+    const unsigned P = (unsigned)plane;
 #pragma unroll
     for (int n = 0; n < 12; ++n) {
-        const rsrc_t r = make_rsrc(fout + (long long)(6 * n) * plane, 6u * pb);
+        const rsrc_t r = make_rsrc(fout + (long long)(6 * n) * plane, 6u * P * (unsigned)sizeof(S));
+        S v[6];
 #pragma unroll
-        for (int s = 0; s < 6; ++s) bstore<S>((S)f[6 * n + s], r, vo, (unsigned)s * pb);
+        for (int s = 0; s < 6; ++s) v[s] = (S)f[6 * n + s];
+        Rec<S>::store(r, (unsigned)off, P, v);
     }
 }
 
@@ -657,13 +721,6 @@ __device__ __forceinline__ void store(S *__restrict__ fout, long long plane, int
 // values with the bilinear weights and the deviations with the weights times the
 // source scales.
 struct Dev16 {};
-
-typedef unsigned int u32x3 __attribute__((ext_vector_type(3)));
-typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
-
-// Vector elements are copied to scalars before a bit cast: clang takes
-// __builtin_bit_cast of an ext_vector element as a cast of element 0.
-__device__ __forceinline__ float u32_as_float(unsigned u) { return __builtin_bit_cast(float, u); }
 
 // half k (0..5) of a cell's packed deviations
 __device__ __forceinline__ float dev_half(const u32x3 &v, int k) {

@@ -97,6 +97,36 @@ def lib():
     return _LIB
 
 
+def unpack_populations(buf, precision, nx, ny):
+    """(72, ny, nx) populations, q = 6 n + k, from an FP32/FP64 buffer in the library's
+    layout: per direction n a block of nx*ny cell records, FP32 shells 0..3 (16 bytes
+    each cell) followed by shells 4..5 (8 bytes), FP64 shell pairs (0,1), (2,3),
+    (4,5) as three runs of 16-byte records.  Returns a new tensor."""
+    P = nx * ny
+    blk = buf.reshape(12, 6 * P)
+    if precision == "fp32":
+        rec = torch.cat([blk[:, :4 * P].reshape(12, P, 4), blk[:, 4 * P:].reshape(12, P, 2)], dim=2)
+    elif precision == "fp64":
+        rec = blk.reshape(12, 3, P, 2).permute(0, 2, 1, 3).reshape(12, P, 6)
+    else:
+        raise ValueError("FP16-deviation buffers: use f16dev_views")
+    return rec.permute(0, 2, 1).reshape(72, ny, nx).contiguous()
+
+
+def pack_populations(f, precision):
+    """Inverse of unpack_populations: a flat buffer in the library's layout."""
+    _, ny, nx = f.shape
+    P = nx * ny
+    rec = f.reshape(12, 6, P).permute(0, 2, 1)
+    if precision == "fp32":
+        out = torch.cat([rec[:, :, :4].reshape(12, 4 * P), rec[:, :, 4:].reshape(12, 2 * P)], dim=1)
+    elif precision == "fp64":
+        out = rec.reshape(12, P, 3, 2).permute(0, 2, 1, 3)
+    else:
+        raise ValueError("FP16-deviation buffers cannot be packed from populations")
+    return out.reshape(-1).contiguous()
+
+
 def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
 
@@ -113,7 +143,7 @@ def _grid_args(params, init, device, stream):
     if prec == "f16dev":
         f = [torch.empty(F16DEV_BYTES_PER_CELL * nx * ny // 4, dtype=torch.float32, device=device) for _ in range(2)]
     else:
-        f = [torch.empty((72, ny, nx), dtype=DTYPE[prec], device=device) for _ in range(2)]
+        f = [torch.empty(72 * nx * ny, dtype=DTYPE[prec], device=device) for _ in range(2)]
     bc = params.get("bc", ("periodic",) * 4)
     tw = params.get("theta_wall", (1.0, 1.0))
     p = Params(nx=nx, ny=ny, stats=STATS[params.get("stats", "MJ")], order=int(params.get("order", 5)),
@@ -167,8 +197,20 @@ class Sim:
         _check(lib().rlbm_step(self.ctx, int(nsteps)), "rlbm_step")
 
     def state(self):
-        """The tensor (72, ny, nx) holding the current post-collision populations."""
+        """The buffer holding the current post-collision state (library layout)."""
         return self.f[lib().rlbm_state_index(self.ctx)]
+
+    def populations(self):
+        """Current post-collision populations as a (72, ny, nx) tensor (FP32/FP64)."""
+        self.sync()
+        return unpack_populations(self.state(), self.precision, self.nx, self.ny)
+
+    def set_populations(self, f):
+        """Overwrite the current state with populations f of shape (72, ny, nx)."""
+        self.sync()
+        st = self.state()
+        st.copy_(pack_populations(f.to(device=st.device, dtype=st.dtype), self.precision))
+        torch.cuda.synchronize(st.device)
 
     def load_state(self, saved):
         """Resume from a saved post-collision state (a tensor like state()): the

@@ -29,7 +29,7 @@ def test_lower_order_parity(rl, order, bc):
                  {k: v.cuda() for k, v in fields.items()})
     sim.step(nsteps)
     got = {k: v.cpu().numpy() for k, v in sim.fields().items()}
-    pops = sim.state().cpu().numpy()
+    pops = sim.populations().cpu().numpy()
     sim.close()
     op = L.Params(stats="MJ", nx=nx, ny=ny, order=order, tau=0.9, bc=dict(xlo=bc, xhi=bc, ylo=bc, yhi=bc))
     f = L.init_state(op, fields["theta"].numpy(), fields["ux"].numpy(), fields["uy"].numpy(), z=fields["z"].numpy())

@@ -82,7 +82,7 @@ def _run(rl, stats, precision, params, fields, nsteps):
     print(f"[parity] {stats} {precision} {params['nx']}x{params['ny']} bc={params.get('bc')} steps={nsteps}", flush=True)
     sim = rl.Sim(params, {k: v.cuda() for k, v in fields.items()})
     sim.step(nsteps)
-    pops = sim.state().double().cpu().numpy()
+    pops = sim.populations().double().cpu().numpy()
     flds = {k: v.cpu().numpy() for k, v in sim.fields().items()}
     sim.close()
     op = _oracle_params(params, stats)
@@ -150,9 +150,9 @@ def test_fp64_single_step_from_oracle_state(rl, stats):
         f, _ = L.step(f, op)
     print(f"[parity] {stats} single step from oracle state {nx}x{ny}", flush=True)
     sim = rl.Sim(dict(nx=nx, ny=ny, stats=stats, precision="fp64", tau=0.7), {k: v.cuda() for k, v in fields.items()})
-    sim.state().copy_(torch.from_numpy(f))
+    sim.set_populations(torch.from_numpy(f))
     sim.step(1)
-    pops = sim.state().cpu().numpy()
+    pops = sim.populations().cpu().numpy()
     flds = {k: v.cpu().numpy() for k, v in sim.fields().items()}
     sim.close()
     f1, _ = L.step(f, op)

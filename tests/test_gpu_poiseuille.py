@@ -51,7 +51,7 @@ def test_forced_walls_parity_fp64(rl, stats):
     sim = rl.Sim(params, {k: v.cuda() for k, v in fields.items()})
     sim.step(steps)
     got = {k: v.cpu().numpy() for k, v in sim.fields().items()}
-    pops = sim.state().cpu().numpy()
+    pops = sim.populations().cpu().numpy()
     sim.close()
     op = _oracle_params(params, stats)
     f0 = {k: v.numpy() for k, v in fields.items()}
