@@ -1,0 +1,50 @@
+"""Host-side conversion between (72, ny, nx) populations and the library's buffer
+layouts (no GPU): FP32/FP64 cell records per direction block, and the FP16-deviation
+buffer's rearranged views.  Layout as documented in include/rlbm.h."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1709_09073_amd import rlbm
+
+
+@pytest.mark.parametrize("precision,dtype", [("fp32", torch.float32), ("fp64", torch.float64)])
+def test_pack_unpack_round_trip(precision, dtype):
+    nx, ny = 7, 5
+    f = torch.randn(72, ny, nx, dtype=dtype, generator=torch.Generator().manual_seed(3))
+    buf = rlbm.pack_populations(f, precision)
+    assert buf.shape == (72 * nx * ny,)
+    assert torch.equal(rlbm.unpack_populations(buf, precision, nx, ny), f)
+
+
+@pytest.mark.parametrize("precision,dtype", [("fp32", torch.float32), ("fp64", torch.float64)])
+def test_record_positions(precision, dtype):
+    """Byte offsets of direction n, shell k, cell c = y nx + x, in elements."""
+    nx, ny = 6, 4
+    P = nx * ny
+    f = torch.arange(72 * P, dtype=dtype).reshape(72, ny, nx)
+    buf = rlbm.pack_populations(f, precision)
+    for n, k, x, y in [(0, 0, 0, 0), (3, 5, 2, 3), (11, 3, 5, 1), (7, 4, 1, 2)]:
+        c = y * nx + x
+        if precision == "fp32":
+            idx = n * 6 * P + (4 * c + k if k < 4 else 4 * P + 2 * c + (k - 4))
+        else:
+            idx = n * 6 * P + (k // 2) * 2 * P + 2 * c + (k % 2)
+        assert buf[idx] == f[6 * n + k, y, x]
+
+
+def test_f16dev_views_layout():
+    nx, ny = 5, 3
+    P = nx * ny
+    raw = torch.zeros(180 * P, dtype=torch.uint8)
+    dev = torch.arange(72 * P, dtype=torch.float16)          # exact in half precision
+    side = torch.arange(9 * P, dtype=torch.float32) + 0.5
+    raw[:144 * P] = dev.view(torch.uint8)
+    raw[144 * P:] = side.view(torch.uint8)
+    d, s = rlbm.f16dev_views(raw.view(torch.float32), nx, ny)
+    for n, k, x, y in [(0, 0, 0, 0), (4, 5, 3, 2), (11, 1, 4, 1)]:
+        c = y * nx + x
+        assert d[6 * n + k, y, x] == dev[n * 6 * P + 6 * c + k]
+    for j, x, y in [(0, 0, 0), (8, 4, 2), (5, 2, 1)]:
+        c = y * nx + x
+        assert s[j, y, x] == side[9 * c + j]
