@@ -1,0 +1,206 @@
+"""Parity at the full workload sizes, in the launch configuration bench.py times
+(autotuned tile, graph-replayed steps, network guess where bench uses it), on sampled
+cells: after K steps the GPU state around a sampled cell (a 5 x 5 window, clipped at
+the grid's edges, whose boundary rules it then keeps) goes through one oracle step
+in FP64, and the oracle's post-collision populations of the centre cell are compared
+with the GPU's after its own next step.
+
+Bars are set on the scale of f_i / w_k, the variable the expansion works in: with
+M = max_i |f_i / w_k| of the oracle's result for the cell, FP32 populations must agree
+to 4e-6 w_k M (FP32 storage and arithmetic from the same FP32 inputs), FP16
+deviations to the re-encoding bound w_k s 2^-11 of the new state plus 4e-6 w_k M.
+(A bar relative to each shell's own largest value would fail where the expanded
+equilibrium of a shell passes through zero: the Bose-Einstein shell 4 does near
+z = 0.55 at theta = 1, where its populations are 1e-4 of their neighbours'.)"""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import lattice as L
+from oracle import quadrature as Q
+
+pytestmark = pytest.mark.gpu
+
+R = 2   # window radius
+
+
+@pytest.fixture(scope="module")
+def rl():
+    from paper_1709_09073_amd import rlbm
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return rlbm
+
+
+@pytest.fixture(scope="module")
+def nets(rl):
+    """Guess networks trained as bench.py trains them (512^2 runs of each family)."""
+    out = {}
+    for name, make in (("FD", lambda: workloads.hotspot_fd(L=512, seed=11, sigma=16.0, device="cuda")),
+                       ("BE", lambda: workloads.hotspot_be(L=512, seed=11, device="cuda"))):
+        params, fields = make()
+        sim = rl.Sim(dict(params, precision="fp32"), fields)
+        sim.step(100)
+        x, t = sim.inversion_samples()
+        sim.close()
+        net = rl.GuessNet()
+        noise = torch.from_numpy(np.random.default_rng(0).standard_normal(rl.MLP_HIDDEN + 1).astype(np.float32)).cuda()
+        net.init(x, t, noise)
+        net.train(x, t, iters=1000, lr=3e-3)
+        out[name] = net
+    return out
+
+
+def _sample_cells(nx, ny, rng, n_interior=40):
+    cells = [(0, 0), (nx - 1, ny - 1), (0, ny // 2), (nx // 2, 0), (nx - 1, ny // 3), (nx // 3, ny - 1)]
+    xs = rng.integers(0, nx, n_interior)
+    ys = rng.integers(0, ny, n_interior)
+    return cells + list(zip(xs.tolist(), ys.tolist()))
+
+
+def _window(x, y, nx, ny, bc):
+    """Window bounds and the oracle's boundary rules for the cut sides (None if the
+    window would have to wrap around a periodic side)."""
+    x0, x1, y0, y1 = x - R, x + R + 1, y - R, y + R + 1
+    sides = {}
+    for side, lo, cut in (("xlo", x0 < 0, x0), ("xhi", x1 > nx, x1), ("ylo", y0 < 0, y0), ("yhi", y1 > ny, y1)):
+        rule = bc[("xlo", "xhi", "ylo", "yhi").index(side)]
+        if lo:
+            if rule == "periodic":
+                return None
+            sides[side] = rule
+        else:
+            sides[side] = "open"   # interior cut: only the centre's result is used
+    return (max(x0, 0), min(x1, nx), max(y0, 0), min(y1, ny)), sides
+
+
+def _check_sampled(rl, params, fields, stats, precision, steps, net=None, seed=0, label=""):
+    nx, ny = params["nx"], params["ny"]
+    p = dict(params, stats=stats, precision=precision)
+    if net is not None:
+        p.update(guess="mlp", mlp=net.w)
+    sim = rl.Sim(p, fields)
+    tile = sim.autotune(trial_steps=3)
+    sim.capture()
+    sim.step(steps)
+    if precision == "f16dev":
+        def full():
+            d, s = rl.f16dev_views(sim.state(), nx, ny)
+            return d, s
+        d0, s0 = full()
+    else:
+        f0 = sim.populations()
+    bc = params["bc"]
+    rng = np.random.default_rng(seed)
+    cells = [c for c in _sample_cells(nx, ny, rng) if _window(*c, nx, ny, bc) is not None]
+    v = Q.vectors(stats)
+    w = v["w"][:, None, None]
+    wins = []
+    for (x, y) in cells:
+        (a0, a1, b0, b1), sides = _window(x, y, nx, ny, bc)
+        if precision == "f16dev":
+            e = d0[:, b0:b1, a0:a1].double().cpu().numpy()
+            sd = s0[:, b0:b1, a0:a1].double().cpu().numpy()
+            Rr = sd[v["k"]] + v["p0"][:, None, None] * (sd[6] * v["vx"][:, None, None] + sd[7] * v["vy"][:, None, None])
+            fw = w * (Rr + sd[8] * e)
+        else:
+            fw = f0[:, b0:b1, a0:a1].double().cpu().numpy()
+        wins.append((x, y, a0, b0, fw, sides))
+    sim.step(1)
+    if precision == "f16dev":
+        d1, s1 = full()
+    else:
+        f1 = sim.populations()
+    sim.close()
+    worst = 0.0
+    for (x, y, a0, b0, fw, sides) in wins:
+        op = L.Params(stats=stats, nx=fw.shape[2], ny=fw.shape[1], tau_mode=params.get("tau_mode", "const"),
+                      tau=params.get("tau", 1.0), tau_a=params.get("tau_a", 2.0), tau_b=params.get("tau_b", 0.2546),
+                      bc=sides, theta_wall=dict(xlo=params.get("theta_wall", (1.0, 1.0))[0],
+                                                xhi=params.get("theta_wall", (1.0, 1.0))[1]))
+        ref, _ = L.step(fw, op)
+        rc = ref[:, y - b0, x - a0]
+        M = np.abs(rc / v["w"]).max()
+        if precision == "f16dev":
+            e = d1[:, y, x].double().cpu().numpy()
+            sd = s1[:, y, x].double().cpu().numpy()
+            Rr = sd[v["k"]] + v["p0"] * (sd[6] * v["vx"] + sd[7] * v["vy"])
+            got = v["w"] * (Rr + sd[8] * e)
+            bound = v["w"] * (sd[8] * 2.0 ** -11 * 1.01 + 4e-6 * M)
+        else:
+            got = f1[:, y, x].double().cpu().numpy()
+            bound = 4e-6 * v["w"] * M
+        r = (np.abs(got - rc) / bound).max()
+        worst = max(worst, r)
+    print(f"  {label}: {len(wins)} sampled cells, tile {tile}, worst error / bar = {worst:.3f}", flush=True)
+    assert worst <= 1.0
+
+
+def test_fd_hotspot_2048_fp32(rl, nets):
+    params, fields = workloads.hotspot_fd(L=2048, device="cuda")
+    _check_sampled(rl, params, fields, "FD", "fp32", 40, net=nets["FD"], seed=1, label="FD hot spot 2048^2 FP32")
+
+
+def test_fd_hotspot_2048_f16dev(rl, nets):
+    params, fields = workloads.hotspot_fd(L=2048, device="cuda")
+    _check_sampled(rl, params, fields, "FD", "f16dev", 40, net=nets["FD"], seed=2,
+                   label="FD hot spot 2048^2 FP16 deviations")
+
+
+def test_be_hotspot_8192_fp32(rl, nets):
+    params, fields = workloads.hotspot_be(L=8192, device="cuda")
+    _check_sampled(rl, params, fields, "BE", "fp32", 20, net=nets["BE"], seed=3, label="BE hot spot 8192^2 FP32")
+
+
+def test_be_hotspot_8192_f16dev(rl, nets):
+    params, fields = workloads.hotspot_be(L=8192, device="cuda")
+    _check_sampled(rl, params, fields, "BE", "f16dev", 20, net=nets["BE"], seed=4,
+                   label="BE hot spot 8192^2 FP16 deviations")
+
+
+def test_taylor_green_512_fp32(rl):
+    params, fields = workloads.taylor_green(L=512, tau=0.8, device="cuda")
+    _check_sampled(rl, params, fields, "MJ", "fp32", 200, seed=5, label="Taylor-Green 512^2 FP32")
+
+
+def test_batch_64_fp32(rl):
+    """The 64-grid transport sweep in one launch (autotuned, graph-replayed):
+    sampled cells of several grids, walls included, against one oracle step."""
+    import bench
+    plist, flist = bench.build_batch("cuda")
+    for p in plist:
+        p["precision"] = "fp32"
+    b = rl.Batch(plist, flist)
+    tile = b.autotune(trial_steps=3)
+    b.capture()
+    b.step(30)
+    rng = np.random.default_rng(7)
+    grids = [0, 1, 17, 40, 63]
+    wins = []
+    before = {g: rl.unpack_populations(b.state(g), "fp32", plist[g]["nx"], plist[g]["ny"]) for g in grids}
+    for g in grids:
+        p = plist[g]
+        nx, ny = p["nx"], p["ny"]
+        cells = [c for c in _sample_cells(nx, ny, rng, n_interior=8) if _window(*c, nx, ny, p["bc"]) is not None]
+        for (x, y) in cells:
+            (a0, a1, b0, b1), sides = _window(x, y, nx, ny, p["bc"])
+            wins.append((g, x, y, a0, b0, before[g][:, b0:b1, a0:a1].double().cpu().numpy(), sides))
+    b.step(1)
+    after = {g: rl.unpack_populations(b.state(g), "fp32", plist[g]["nx"], plist[g]["ny"]) for g in grids}
+    b.close()
+    v = Q.vectors("MJ")
+    worst = 0.0
+    for (g, x, y, a0, b0, fw, sides) in wins:
+        p = plist[g]
+        tw = p.get("theta_wall", (1.0, 1.0))
+        op = L.Params(stats="MJ", nx=fw.shape[2], ny=fw.shape[1], tau=p["tau"], bc=sides,
+                      theta_wall=dict(xlo=tw[0], xhi=tw[1]))
+        ref, _ = L.step(fw, op)
+        rc = ref[:, y - b0, x - a0]
+        got = after[g][:, y, x].double().cpu().numpy()
+        M = np.abs(rc / v["w"]).max()
+        worst = max(worst, (np.abs(got - rc) / (4e-6 * v["w"] * M)).max())
+    print(f"  batch of 64: {len(wins)} sampled cells in grids {grids}, tile {tile}, worst error / bar = {worst:.3f}",
+          flush=True)
+    assert worst <= 1.0
