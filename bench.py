@@ -311,6 +311,13 @@ def main():
         vsteps = max(100, min(args.steps, 500))
         out["variants"] = {"unit": "MLUPS", "steps": vsteps, **variants(args.workload, net, vsteps)}
         out["error_vs_fp64"] = error_vs_fp64(args.workload)
+        v, e = out["variants"], out["error_vs_fp64"]
+        if "f16dev_mlp" in v and e:
+            # FP16-deviation storage with the network guess against plain FP32 (fixed guess)
+            out["reduced_vs_plain"] = {"reduced_mlups": v["f16dev_mlp"], "plain_fp32_mlups": v["fp32_fixed"],
+                                       "speedup": round(v["f16dev_mlp"] / v["fp32_fixed"], 4),
+                                       "reduced_eps_theta": e["f16dev"]["eps_theta"],
+                                       "reduced_eps_q": e["f16dev"]["eps_q"], "error_bar": 1e-3}
     if not args.no_cpu_baseline and args.workload != "batched_sweep_64":
         out["cpu_baseline"] = cpu_baseline(args.workload)
     print(json.dumps(out), flush=True)
