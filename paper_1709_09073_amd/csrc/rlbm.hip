@@ -277,7 +277,9 @@ struct Mom {
     double N0, Nx, Ny, T00, T01, T02, T11, T12, T22;
 };
 
-template <int ST, typename R>
+// GU: f holds f_i / w_k (the FP16-deviation path works in those units); the
+// weights fold into the constants.
+template <int ST, typename R, bool GU = false>
 __device__ __forceinline__ Mom moments(const R (&f)[72]) {
     Mom m{0, 0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
@@ -285,9 +287,9 @@ __device__ __forceinline__ Mom moments(const R (&f)[72]) {
         R a = 0, b = 0;
 #pragma unroll
         for (int s = 0; s < 6; ++s) {
-            const R p = (R)P_SHELL[ST][s];
-            a += f[6 * n + s] * p;
-            b += f[6 * n + s] * (p * p);
+            const double w = GU ? W_SHELL[ST][s] : 1.0;
+            a += f[6 * n + s] * (R)(P_SHELL[ST][s] * w);
+            b += f[6 * n + s] * (R)(P_SHELL[ST][s] * P_SHELL[ST][s] * w);
         }
         const double A = (double)a, B = (double)b, c = cdir(n), sn = sdir(n);
         m.N0 += A;
@@ -604,7 +606,8 @@ __device__ __forceinline__ constexpr double emat(int pair, int shell) {
 
 enum { EQ_SET = 0, EQ_COLLIDE = 1, EQ_NEQ = 2, EQ_ADD = 3 };
 
-template <int ST, int MODE, typename R, int N = 5>
+// GU: f holds f_i / w_k and receives f^eq_i / w_k (the 1/w_k folds into the projector).
+template <int ST, int MODE, typename R, int N = 5, bool GU = false>
 __device__ __forceinline__ void equilibrium_relax(const Macro &M, double tau, R (&f)[72]) {
     constexpr bool COLLIDE = MODE == EQ_COLLIDE || MODE == EQ_NEQ;
     static_assert(N == 5 || (ST == RLBM_MJ && N >= 2 && N <= 4), "lower orders are tabulated for MJ");
@@ -668,7 +671,8 @@ __device__ __forceinline__ void equilibrium_relax(const Macro &M, double tau, R 
             double acc = 0.0;
             if (j <= N) {
 #pragma unroll
-                for (int k = j; k <= N; ++k) acc += emat<ST, N>(pair_index(j, k), s) * h[pair_index(j, k)];
+                for (int k = j; k <= N; ++k)
+                    acc += (emat<ST, N>(pair_index(j, k), s) * (GU ? 1.0 / W_SHELL[ST][s] : 1.0)) * h[pair_index(j, k)];
             }
             r[j] = (R)acc;
         }
@@ -768,7 +772,7 @@ __device__ __forceinline__ void dev_direction(const char *base, long long plane,
         float acc = rb[k] + (float)P_SHELL[ST][k] * tn;
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc += ws[t] * dev_half(d[t], k);
-        f[6 * N + k] = (float)W_SHELL[ST][k] * acc;
+        f[6 * N + k] = acc;   // f_i / w_k
     }
 }
 
@@ -810,12 +814,13 @@ __device__ __forceinline__ void pull_dev(const void *fin, long long plane, int n
     dev_direction<ST, 11, 4>(base, plane, {ul, cl, uc, cc}, {wA, wA, wB, wB}, {&D, &A, &B, &C}, f);
 }
 
+// f holds f_i / w_k.
 template <int ST>
 __device__ __forceinline__ void store_dev(void *fout, long long plane, int off, const float (&f)[72]) {
     char *base = (char *)fout;
     float g[72];
 #pragma unroll
-    for (int q = 0; q < 72; ++q) g[q] = f[q] * (float)(1.0 / W_SHELL[ST][q % 6]);
+    for (int q = 0; q < 72; ++q) g[q] = f[q];
     float rho[6], A = 0.0f, B = 0.0f;
     double pp = 0.0;
 #pragma unroll
@@ -893,7 +898,7 @@ __device__ __forceinline__ void step_cell(const KArgs &a, int x, int y) {
     R f[72];
     if constexpr (std::is_same<S, Dev16>::value) pull_dev<ST>(a.fin, a.plane, a.nx, xe, ye, xl, xr, yd, yu, f);
     else pull<S, R>((const S *)a.fin, a.plane, a.nx, xe, ye, xl, xr, yd, yu, f);
-    const Mom m = moments<ST, R>(f);
+    const Mom m = moments<ST, R, std::is_same<S, Dev16>::value>(f);
     Macro M;
     int iters;
     state_from_moments<ST, sizeof(R) == 4>(m, M, flags, a, iters);
@@ -911,7 +916,7 @@ __device__ __forceinline__ void step_cell(const KArgs &a, int x, int y) {
         // zeroth-order extrapolation of n and u, fixed wall temperature
         const double n = M.n;
         state_from_n_theta<ST>(n, wall_lo ? a.th_wall_lo : a.th_wall_hi, M, flags);
-        equilibrium_relax<ST, EQ_SET, R, N>(M, 1.0, f);
+        equilibrium_relax<ST, EQ_SET, R, N, std::is_same<S, Dev16>::value>(M, 1.0, f);
     } else {
         const double tau = (a.tau_mode == RLBM_TAU_CONST) ? a.tau : a.tau_a / M.theta + a.tau_b;
         if constexpr (FORCED) {
@@ -925,16 +930,16 @@ __device__ __forceinline__ void step_cell(const KArgs &a, int x, int y) {
             M.ga = 1.0 / sqrt(1.0 - (M.ux * M.ux + M.uy * M.uy));
             if (neq_lo || neq_hi) {
                 // wall row: f^eq(wall_n, wall_theta, u = 0) + (f* - f^eq) of the fluid neighbour
-                equilibrium_relax<ST, EQ_NEQ, R, N>(M, tau, f);
+                equilibrium_relax<ST, EQ_NEQ, R, N, std::is_same<S, Dev16>::value>(M, tau, f);
                 state_from_n_theta<ST>(a.wall_n, a.wall_theta, M, flags);
                 M.ux = M.uy = 0.0;
                 M.ga = 1.0;
-                equilibrium_relax<ST, EQ_ADD, R, N>(M, 1.0, f);
+                equilibrium_relax<ST, EQ_ADD, R, N, std::is_same<S, Dev16>::value>(M, 1.0, f);
             } else {
-                equilibrium_relax<ST, EQ_COLLIDE, R, N>(M, tau, f);
+                equilibrium_relax<ST, EQ_COLLIDE, R, N, std::is_same<S, Dev16>::value>(M, tau, f);
             }
         } else {
-            equilibrium_relax<ST, EQ_COLLIDE, R, N>(M, tau, f);
+            equilibrium_relax<ST, EQ_COLLIDE, R, N, std::is_same<S, Dev16>::value>(M, tau, f);
         }
     }
     if constexpr (std::is_same<S, Dev16>::value) store_dev<ST>(a.fout, a.plane, y * a.nx + x, f);
@@ -1010,7 +1015,7 @@ __global__ __launch_bounds__(256) void k_moments(KArgs a) {
     R f[72];
     if constexpr (std::is_same<S, Dev16>::value) pull_dev<ST>(a.fin, a.plane, a.nx, x, y, xl, xr, yd, yu, f);
     else pull<S, R>((const S *)a.fin, a.plane, a.nx, x, y, xl, xr, yd, yu, f);
-    const Mom m = moments<ST, R>(f);
+    const Mom m = moments<ST, R, std::is_same<S, Dev16>::value>(f);
     Macro M;
     int iters;
     double L;
@@ -1031,7 +1036,7 @@ __global__ __launch_bounds__(256) void k_moments(KArgs a) {
 }
 
 // sum_i f_i (p_i^x)^r for r = 2..5, in FP64: p^x = p_k cos(phi_n).
-template <int ST, typename R>
+template <int ST, typename R, bool GU = false>
 __device__ __forceinline__ void px_powers(const R (&f)[72], double (&o)[4]) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) o[r] = 0.0;
@@ -1041,7 +1046,7 @@ __device__ __forceinline__ void px_powers(const R (&f)[72], double (&o)[4]) {
         double a[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
-            const double p = P_SHELL[ST][k], v = (double)f[6 * n + k];
+            const double p = P_SHELL[ST][k], v = (double)f[6 * n + k] * (GU ? W_SHELL[ST][k] : 1.0);
             a[0] += v * (p * p);
             a[1] += v * (p * p * p);
             a[2] += v * (p * p * p * p);
@@ -1068,14 +1073,14 @@ __global__ __launch_bounds__(256) void k_noneq(KArgs a) {
     R f[72];
     if constexpr (std::is_same<S, Dev16>::value) pull_dev<ST>(a.fin, a.plane, a.nx, x, y, xl, xr, yd, yu, f);
     else pull<S, R>((const S *)a.fin, a.plane, a.nx, x, y, xl, xr, yd, yu, f);
-    const Mom m = moments<ST, R>(f);
+    const Mom m = moments<ST, R, std::is_same<S, Dev16>::value>(f);
     Macro M;
     int iters;
     state_from_moments<ST, sizeof(R) == 4>(m, M, flags, a, iters);
     double sf[4], se[4];
-    px_powers<ST, R>(f, sf);
-    equilibrium_relax<ST, EQ_SET, R, N>(M, 1.0, f);   // f <- f^eq
-    px_powers<ST, R>(f, se);
+    px_powers<ST, R, std::is_same<S, Dev16>::value>(f, sf);
+    equilibrium_relax<ST, EQ_SET, R, N, std::is_same<S, Dev16>::value>(M, 1.0, f);   // f <- f^eq
+    px_powers<ST, R, std::is_same<S, Dev16>::value>(f, se);
     const int off = y * a.nx + x;
 #pragma unroll
     for (int r = 0; r < 4; ++r)
@@ -1102,7 +1107,7 @@ __global__ __launch_bounds__(256) void k_init(KArgs a) {
     if (a.given_z) state_from_z_theta<ST>(a.i_z[off], th, M, flags);
     else state_from_n_theta<ST>(a.i_n[off], th, M, flags);
     R f[72];
-    equilibrium_relax<ST, EQ_SET, R, N>(M, 1.0, f);
+    equilibrium_relax<ST, EQ_SET, R, N, std::is_same<S, Dev16>::value>(M, 1.0, f);
     if constexpr (std::is_same<S, Dev16>::value) store_dev<ST>(a.fout, a.plane, off, f);
     else store<S, R>((S *)a.fout, a.plane, off, f);
     report(a.status, flags);
