@@ -235,8 +235,7 @@ def main():
                     help="FD/BE inversion start: fixed, or the network trained on a smaller run first")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the domain-decomposed design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path", file=sys.stderr)
         raise SystemExit(2)
 
     import torch

@@ -12,7 +12,8 @@ the bars scale with g(K) = max(1, K/100):
     (2e-12, 2e-12, 2e-12, 5e-12, 2e-11, 2e-10) g(K); the outer shells carry the rounding
     of the ill-conditioned radial projection.
 One step from the same non-equilibrium state must agree to 1e-13 in the fields.
-FP32 populations: bars derived from 2^-24 storage rounding.
+FP32 populations: bars from the 2^-24 storage rounding per step, amplified by the
+inversion (theta, z) and by the cancellation in q = n U - N.
 """
 import numpy as np
 import pytest

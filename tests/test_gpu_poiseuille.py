@@ -1,7 +1,7 @@
 """Forced flow and non-equilibrium-extrapolation walls on the GPU (Sec. 3.4):
 parity with the FP64 oracle, then the Poiseuille grid-convergence study.
 
-Convergence reading (see DESIGN.md): on this lattice the shear viscosity for
+Convergence reading: on this lattice the shear viscosity for
 wavevectors along an axis, which is what Poiseuille flow feels, is not the
 Taylor-Green value of Eq. nu-ref-eq (Taylor-Green modes have diagonal wavevectors and
 the interpolated streaming is anisotropic): at tau = 3 it is about 1.5% larger.  The
