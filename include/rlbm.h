@@ -57,7 +57,7 @@ enum rlbm_status_code {
     RLBM_EDOMAIN = -2,    /* a kernel flagged a state outside the method's domain */
     RLBM_EHIP = -3,       /* a HIP runtime call failed */
     RLBM_ENONFINITE = -4, /* a kernel produced a non-finite field */
-    RLBM_ENOTIMPL = -5    /* valid request this build does not support */
+    RLBM_ENOTIMPL = -5    /* valid request the library does not implement */
 };
 
 enum rlbm_stats { RLBM_MJ = 0, RLBM_FD = 1, RLBM_BE = 2 };         /* Eqs. mj-w-eq, fd-w-eq, be-w-eq */

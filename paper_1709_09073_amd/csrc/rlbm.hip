@@ -1697,7 +1697,7 @@ const char *rlbm_strerror(int code) {
         case RLBM_EDOMAIN: return "state outside the method's domain (see rlbm_status bits)";
         case RLBM_EHIP: return "HIP runtime error";
         case RLBM_ENONFINITE: return "non-finite field";
-        case RLBM_ENOTIMPL: return "not supported by this build";
+        case RLBM_ENOTIMPL: return "not implemented by the library";
         default: return "unknown status code";
     }
 }
