@@ -734,45 +734,52 @@ __device__ __forceinline__ float dev_half(const u32x3 &v, int k) {
 }
 
 struct SideRef {
-    float v[9];   // rho_0..rho_5, alpha, beta, s
+    float v[8];   // rho_0..rho_5, alpha, beta
+    float s;      // scale
 };
 
 __device__ __forceinline__ void load_side(rsrc_t rs, unsigned cell, SideRef &o) {
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
         const u32x3 w = __builtin_amdgcn_raw_buffer_load_b96(rs, cell * 36u, (unsigned)j * 12u, LOAD_POLICY);
-        o.v[3 * j] = u32_as_float(w[0]);
-        o.v[3 * j + 1] = u32_as_float(w[1]);
-        o.v[3 * j + 2] = u32_as_float(w[2]);
+        const float a = u32_as_float(w[0]), b = u32_as_float(w[1]), c = u32_as_float(w[2]);
+        o.v[3 * j] = a;
+        o.v[3 * j + 1] = b;
+        if (j < 2) o.v[3 * j + 2] = c;
+        else o.s = c;
     }
 }
 
-// One direction n with taps (cell index, weight, side values).
+// One direction n: taps (cell index, weight times the source's scale) and the side
+// values already interpolated to the departure point (rho_0..rho_5, alpha, beta).
 template <int ST, int N, int NT>
 __device__ __forceinline__ void dev_direction(const char *base, long long plane, const unsigned (&cell)[NT],
-                                              const float (&wt)[NT], const SideRef *const (&sd)[NT], float (&f)[72]) {
+                                              const float (&ws)[NT], const float (&iv)[8], float (&f)[72]) {
     const rsrc_t r = make_rsrc(base + (long long)N * plane * 12, 12u * (unsigned)plane);
     u32x3 d[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) d[t] = __builtin_amdgcn_raw_buffer_load_b96(r, cell[t] * 12u, 0u, LOAD_POLICY);
-    float rb[6], ab = 0.0f, bb = 0.0f, ws[NT];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) rb[k] = 0.0f;
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-#pragma unroll
-        for (int k = 0; k < 6; ++k) rb[k] += wt[t] * sd[t]->v[k];
-        ab += wt[t] * sd[t]->v[6];
-        bb += wt[t] * sd[t]->v[7];
-        ws[t] = wt[t] * sd[t]->v[8];
-    }
-    const float tn = ab * (float)cdir(N) + bb * (float)sdir(N);
+    const float tn = iv[6] * (float)cdir(N) + iv[7] * (float)sdir(N);
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-        float acc = rb[k] + (float)P_SHELL[ST][k] * tn;
+        float acc = iv[k] + (float)P_SHELL[ST][k] * tn;
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc += ws[t] * dev_half(d[t], k);
         f[6 * N + k] = acc;   // f_i / w_k
+    }
+}
+
+// The two off-axis directions of a quadrant pull from the same four cells: D (the
+// diagonal neighbour), A and B (the neighbours along x and y) and C (the cell).  One
+// weights (D, A, B, C) by (wA, wA, wB, wB), the other by (wA, wB, wA, wB); the part
+// wA D + wB C is shared.
+__device__ __forceinline__ void quad_interp(const SideRef &D, const SideRef &A, const SideRef &B, const SideRef &C,
+                                            float wA, float wB, float (&ia)[8], float (&ib)[8]) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const float k = wA * D.v[j] + wB * C.v[j];
+        ia[j] = k + wA * A.v[j] + wB * B.v[j];
+        ib[j] = k + wB * A.v[j] + wA * B.v[j];
     }
 }
 
@@ -786,35 +793,40 @@ __device__ __forceinline__ void pull_dev(const void *fin, long long plane, int n
     const unsigned uc = yu * nx + x, ul = yu * nx + xl, ur = yu * nx + xr;
     const float wA = (float)(S3H * 0.5), wB = (float)((1.0 - S3H) * 0.5);
     SideRef C, A, B, D;
+    float ia[8], ib[8];
     load_side(rs, cc, C);
-    // quadrant towards -x, -y: directions 0, 3 (axis), 1, 2
+    const float sC = C.s;
+    // quadrant towards -x, -y: A = left, B = down; axis directions 0 and 3
     load_side(rs, cl, A);
     load_side(rs, dc, B);
     load_side(rs, dl, D);
-    dev_direction<ST, 0, 1>(base, plane, {cl}, {1.0f}, {&A}, f);
-    dev_direction<ST, 3, 1>(base, plane, {dc}, {1.0f}, {&B}, f);
-    dev_direction<ST, 1, 4>(base, plane, {dl, cl, dc, cc}, {wA, wA, wB, wB}, {&D, &A, &B, &C}, f);
-    dev_direction<ST, 2, 4>(base, plane, {dl, dc, cl, cc}, {wA, wA, wB, wB}, {&D, &B, &A, &C}, f);
-    // quadrant towards +x, -y: directions 6 (axis), 4, 5 (reuse the -y cell)
+    dev_direction<ST, 0, 1>(base, plane, {cl}, {A.s}, A.v, f);
+    dev_direction<ST, 3, 1>(base, plane, {dc}, {B.s}, B.v, f);
+    quad_interp(D, A, B, C, wA, wB, ia, ib);
+    dev_direction<ST, 1, 4>(base, plane, {dl, cl, dc, cc}, {wA * D.s, wA * A.s, wB * B.s, wB * sC}, ia, f);
+    dev_direction<ST, 2, 4>(base, plane, {dl, dc, cl, cc}, {wA * D.s, wA * B.s, wB * A.s, wB * sC}, ib, f);
+    // quadrant towards +x, -y: A = right, B = down (kept); axis direction 6
     load_side(rs, cr, A);
     load_side(rs, dr, D);
-    dev_direction<ST, 6, 1>(base, plane, {cr}, {1.0f}, {&A}, f);
-    dev_direction<ST, 4, 4>(base, plane, {dr, dc, cr, cc}, {wA, wA, wB, wB}, {&D, &B, &A, &C}, f);
-    dev_direction<ST, 5, 4>(base, plane, {dr, cr, dc, cc}, {wA, wA, wB, wB}, {&D, &A, &B, &C}, f);
-    // quadrant towards +x, +y: directions 9 (axis), 7, 8 (reuse the +x cell)
+    dev_direction<ST, 6, 1>(base, plane, {cr}, {A.s}, A.v, f);
+    quad_interp(D, A, B, C, wA, wB, ia, ib);
+    dev_direction<ST, 4, 4>(base, plane, {dr, dc, cr, cc}, {wA * D.s, wA * B.s, wB * A.s, wB * sC}, ib, f);
+    dev_direction<ST, 5, 4>(base, plane, {dr, cr, dc, cc}, {wA * D.s, wA * A.s, wB * B.s, wB * sC}, ia, f);
+    // quadrant towards +x, +y: A = right (kept), B = up; axis direction 9
     load_side(rs, uc, B);
     load_side(rs, ur, D);
-    dev_direction<ST, 9, 1>(base, plane, {uc}, {1.0f}, {&B}, f);
-    dev_direction<ST, 7, 4>(base, plane, {ur, cr, uc, cc}, {wA, wA, wB, wB}, {&D, &A, &B, &C}, f);
-    dev_direction<ST, 8, 4>(base, plane, {ur, uc, cr, cc}, {wA, wA, wB, wB}, {&D, &B, &A, &C}, f);
-    // quadrant towards -x, +y: directions 10, 11 (reuse the +y cell)
+    dev_direction<ST, 9, 1>(base, plane, {uc}, {B.s}, B.v, f);
+    quad_interp(D, A, B, C, wA, wB, ia, ib);
+    dev_direction<ST, 7, 4>(base, plane, {ur, cr, uc, cc}, {wA * D.s, wA * A.s, wB * B.s, wB * sC}, ia, f);
+    dev_direction<ST, 8, 4>(base, plane, {ur, uc, cr, cc}, {wA * D.s, wA * B.s, wB * A.s, wB * sC}, ib, f);
+    // quadrant towards -x, +y: A = left, B = up (kept)
     load_side(rs, cl, A);
     load_side(rs, ul, D);
-    dev_direction<ST, 10, 4>(base, plane, {ul, uc, cl, cc}, {wA, wA, wB, wB}, {&D, &B, &A, &C}, f);
-    dev_direction<ST, 11, 4>(base, plane, {ul, cl, uc, cc}, {wA, wA, wB, wB}, {&D, &A, &B, &C}, f);
+    quad_interp(D, A, B, C, wA, wB, ia, ib);
+    dev_direction<ST, 10, 4>(base, plane, {ul, uc, cl, cc}, {wA * D.s, wA * B.s, wB * A.s, wB * sC}, ib, f);
+    dev_direction<ST, 11, 4>(base, plane, {ul, cl, uc, cc}, {wA * D.s, wA * A.s, wB * B.s, wB * sC}, ia, f);
 }
 
-// f holds f_i / w_k.
 template <int ST>
 __device__ __forceinline__ void store_dev(void *fout, long long plane, int off, const float (&f)[72]) {
     char *base = (char *)fout;
