@@ -24,7 +24,8 @@ def _numeric_I2(stats, theta, z, ux, uy, nang=256):
             if xi == 0.0:
                 fun = lambda p: p ** K * z * np.exp(-a * p)
             else:
-                fun = lambda p: p ** K / (np.exp(a * p) / z + xi)
+                # exp(-a p) form: no overflow far out in p, where the integrand is zero
+                fun = lambda p: p ** K * np.exp(-a * p) * z / (1.0 + xi * z * np.exp(-a * p))
             rad[i, K] = integrate.quad(fun, 0, np.inf, epsabs=0, epsrel=1e-13, limit=200)[0]
     out = {}
     for (m, n, q) in C.MONOMIALS:
