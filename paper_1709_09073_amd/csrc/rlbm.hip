@@ -66,6 +66,16 @@ __host__ __device__ constexpr double sdir(int n) { return cdir((n + 9) % 12); }
 // cos(j*phi_n), sin(j*phi_n) from the exact table (j*n taken mod 12)
 __host__ __device__ constexpr double cjn(int j, int n) { return cdir((j * n) % 12); }
 __host__ __device__ constexpr double sjn(int j, int n) { return sdir((j * n) % 12); }
+// x c + acc for a factor c that is a compile-time constant once loops are unrolled (a
+// direction cosine, a table entry).  The compiler keeps x * 0 (x may be NaN or
+// infinite), so zero and unit factors are spelled out: they cost nothing or one add.
+template <typename T>
+__device__ __forceinline__ T fma_c(T x, double c, T acc) {
+    if (c == 0.0) return acc;
+    if (c == 1.0) return acc + x;
+    if (c == -1.0) return acc - x;
+    return x * (T)c + acc;
+}
 // index of the pair (j, k), j-major, k = j..5
 __host__ __device__ constexpr int pair_index(int j, int k) { return j * 6 - (j * (j - 1)) / 2 + (k - j); }
 
@@ -281,26 +291,34 @@ struct Mom {
 // weights fold into the constants.
 template <int ST, typename R, bool GU = false>
 __device__ __forceinline__ Mom moments(const R (&f)[72]) {
-    Mom m{0, 0, 0, 0, 0, 0, 0, 0, 0};
+    Mom m{-0.0, -0.0, -0.0, -0.0, -0.0, -0.0, -0.0, -0.0, -0.0};   // -0 + x folds to x
+    // per direction: a = sum_k f p_k, b = sum_k f p_k^2; opposite directions n and
+    // n + 6 share |cos|, |sin|, so their sums (even moments) and differences (odd
+    // moments) enter once
 #pragma unroll
-    for (int n = 0; n < 12; ++n) {
-        R a = 0, b = 0;
+    for (int n = 0; n < 6; ++n) {
+        R a[2] = {0, 0}, b[2] = {0, 0};
 #pragma unroll
-        for (int s = 0; s < 6; ++s) {
-            const double w = GU ? W_SHELL[ST][s] : 1.0;
-            a += f[6 * n + s] * (R)(P_SHELL[ST][s] * w);
-            b += f[6 * n + s] * (R)(P_SHELL[ST][s] * P_SHELL[ST][s] * w);
-        }
-        const double A = (double)a, B = (double)b, c = cdir(n), sn = sdir(n);
-        m.N0 += A;
-        m.Nx += A * c;
-        m.Ny += A * sn;
-        m.T00 += B;
-        m.T01 += B * c;
-        m.T02 += B * sn;
-        m.T11 += B * (c * c);
-        m.T12 += B * (c * sn);
-        m.T22 += B * (sn * sn);
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int s = 0; s < 6; ++s) {
+                const double w = GU ? W_SHELL[ST][s] : 1.0;
+                const R v = f[6 * (n + 6 * h) + s];
+                a[h] += v * (R)(P_SHELL[ST][s] * w);
+                b[h] += v * (R)(P_SHELL[ST][s] * P_SHELL[ST][s] * w);
+            }
+        const double SA = (double)a[0] + (double)a[1], DA = (double)a[0] - (double)a[1];
+        const double SB = (double)b[0] + (double)b[1], DB = (double)b[0] - (double)b[1];
+        const double c = cdir(n), sn = sdir(n);
+        m.N0 += SA;
+        m.Nx = fma_c(DA, c, m.Nx);
+        m.Ny = fma_c(DA, sn, m.Ny);
+        m.T00 += SB;
+        m.T01 = fma_c(DB, c, m.T01);
+        m.T02 = fma_c(DB, sn, m.T02);
+        m.T11 = fma_c(SB, c * c, m.T11);
+        m.T12 = fma_c(SB, c * sn, m.T12);
+        m.T22 = fma_c(SB, sn * sn, m.T22);
     }
     return m;
 }
@@ -604,6 +622,12 @@ __device__ __forceinline__ constexpr double emat(int pair, int shell) {
     else return EMAT_LO[N - 2][pair][shell];
 }
 
+// PKJ[pi][0] + PKJ[pi][1] u^2 + PKJ[pi][2] u^4, with the zero coefficients skipped
+__device__ __forceinline__ double poly_u2(int pi, double u2) {
+    if (PKJ[pi][2] != 0.0) return (u2 * PKJ[pi][2] + PKJ[pi][1]) * u2 + PKJ[pi][0];
+    return fma_c(u2, PKJ[pi][1], PKJ[pi][0]);
+}
+
 enum { EQ_SET = 0, EQ_COLLIDE = 1, EQ_NEQ = 2, EQ_ADD = 3 };
 
 // GU: f holds f_i / w_k and receives f^eq_i / w_k (the 1/w_k folds into the projector).
@@ -629,7 +653,7 @@ __device__ __forceinline__ void equilibrium_relax(const Macro &M, double tau, R 
 #pragma unroll
         for (int k = j; k <= N; ++k) {
             const int pi = pair_index(j, k);
-            h[pi] = G[k] * (PKJ[pi][0] + u2 * (PKJ[pi][1] + u2 * PKJ[pi][2]));
+            h[pi] = G[k] * poly_u2(pi, u2);
         }
     // harmonics (u_x + i u_y)^j
     R C[6], S[6];
@@ -650,7 +674,7 @@ __device__ __forceinline__ void equilibrium_relax(const Macro &M, double tau, R 
     for (int n = 0; n < 6; ++n) {
         A[0][n] = (R)1;
 #pragma unroll
-        for (int j = 1; j < 6; ++j) A[j][n] = C[j] * (R)cjn(j, n) + S[j] * (R)sjn(j, n);
+        for (int j = 1; j < 6; ++j) A[j][n] = fma_c(S[j], sjn(j, n), fma_c(C[j], cjn(j, n), (R)-0.0));
     }
     R om[12];
     if constexpr (COLLIDE) {
@@ -658,7 +682,7 @@ __device__ __forceinline__ void equilibrium_relax(const Macro &M, double tau, R 
         const R ux = (R)M.ux, uy = (R)M.uy;
 #pragma unroll
         for (int n = 0; n < 6; ++n) {
-            const R vu = ux * (R)cdir(n) + uy * (R)sdir(n);
+            const R vu = fma_c(uy, sdir(n), fma_c(ux, cdir(n), (R)-0.0));
             om[n] = gt - gt * vu;
             om[n + 6] = gt + gt * vu;
         }
@@ -759,7 +783,7 @@ __device__ __forceinline__ void dev_direction(const char *base, long long plane,
     u32x3 d[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) d[t] = __builtin_amdgcn_raw_buffer_load_b96(r, cell[t] * 12u, 0u, LOAD_POLICY);
-    const float tn = iv[6] * (float)cdir(N) + iv[7] * (float)sdir(N);
+    const float tn = fma_c(iv[7], sdir(N), fma_c(iv[6], cdir(N), -0.0f));
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
         float acc = iv[k] + (float)P_SHELL[ST][k] * tn;
@@ -827,6 +851,17 @@ __device__ __forceinline__ void pull_dev(const void *fin, long long plane, int n
     dev_direction<ST, 11, 4>(base, plane, {ul, cl, uc, cc}, {wA * D.s, wA * A.s, wB * B.s, wB * sC}, ia, f);
 }
 
+// (a c, b c) rounded once each to IEEE half and packed low, high: v_fma_mix takes the
+// FP32 operands and rounds the exact product (one instruction per value instead of
+// a multiply per value and a conversion per pair).  mixlo leaves the high half of
+// its destination alone; mixhi then writes it.
+__device__ __forceinline__ unsigned scaled_f16x2(float a, float b, float c) {
+    unsigned r;
+    asm("v_fma_mixlo_f16 %0, %1, %2, 0" : "=v"(r) : "v"(a), "v"(c));
+    asm("v_fma_mixhi_f16 %0, %1, %2, 0" : "+v"(r) : "v"(b), "v"(c));
+    return r;
+}
+
 template <int ST>
 __device__ __forceinline__ void store_dev(void *fout, long long plane, int off, const float (&f)[72]) {
     char *base = (char *)fout;
@@ -837,13 +872,18 @@ __device__ __forceinline__ void store_dev(void *fout, long long plane, int off, 
     double pp = 0.0;
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-        float sum = 0.0f, sc = 0.0f, ss = 0.0f;
+        // directions n and n + 6 are opposite: sums e_n = g_n + g_{n+6} enter the
+        // average, differences d_n = g_n - g_{n+6} the dipole
+        float e[6], d[6];
 #pragma unroll
-        for (int n = 0; n < 12; ++n) {
-            sum += g[6 * n + k];
-            sc += g[6 * n + k] * (float)cdir(n);
-            ss += g[6 * n + k] * (float)sdir(n);
+        for (int n = 0; n < 6; ++n) {
+            e[n] = g[6 * n + k] + g[6 * (n + 6) + k];
+            d[n] = g[6 * n + k] - g[6 * (n + 6) + k];
         }
+        const float sum = ((e[0] + e[1]) + (e[2] + e[3])) + (e[4] + e[5]);
+        // cos phi_n = 1, S3H, 1/2, 0, -1/2, -S3H and sin phi_n = 0, 1/2, S3H, 1, S3H, 1/2
+        const float sc = d[0] + (float)S3H * (d[1] - d[5]) + 0.5f * (d[2] - d[4]);
+        const float ss = d[3] + 0.5f * (d[1] + d[5]) + (float)S3H * (d[2] + d[4]);
         rho[k] = sum * (1.0f / 12.0f);
         A += (float)P_SHELL[ST][k] * sc;
         B += (float)P_SHELL[ST][k] * ss;
@@ -855,7 +895,7 @@ __device__ __forceinline__ void store_dev(void *fout, long long plane, int off, 
     float smax = 0.0f;
 #pragma unroll
     for (int n = 0; n < 12; ++n) {
-        const float tn = alpha * (float)cdir(n) + beta * (float)sdir(n);
+        const float tn = fma_c(beta, sdir(n), fma_c(alpha, cdir(n), -0.0f));
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
             g[6 * n + k] -= rho[k] + (float)P_SHELL[ST][k] * tn;
@@ -870,8 +910,7 @@ __device__ __forceinline__ void store_dev(void *fout, long long plane, int off, 
         u32x3 w;
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-            const f16x2 h = {(_Float16)(g[6 * n + 2 * j] * inv), (_Float16)(g[6 * n + 2 * j + 1] * inv)};
-            w[j] = __builtin_bit_cast(unsigned, h);
+            w[j] = scaled_f16x2(g[6 * n + 2 * j], g[6 * n + 2 * j + 1], inv);
         }
         __builtin_amdgcn_raw_buffer_store_b96(w, r, uoff * 12u, 0u, STORE_POLICY);
     }
