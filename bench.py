@@ -264,7 +264,7 @@ def main():
         ncell = sum(p["nx"] * p["ny"] for p in plist)
         params = dict(nx=ncell, ny=1, stats="MJ", grids=len(plist))
         if args.tile == "auto":
-            tile = sim.autotune(trial_steps=5)
+            tile = sim.autotune(trial_steps=10)
             args.tile = f"{tile[0]}x{tile[1]} (autotuned)"
     else:
         sim = rlbm.Sim(params, fields)

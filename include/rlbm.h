@@ -155,9 +155,11 @@ int rlbm_configure(rlbm_ctx *ctx, int32_t tile_x, int32_t tile_y, int32_t persis
 
 /* Time trial_steps steps with each workgroup tile shape in {32x8, 64x4, 16x16,
  * 128x2, 256x1} (one workgroup per tile) and, for a batch, also 32x8 and 64x4 with
- * 96 persistent workgroups per XCD; keep the fastest; the chosen shape is returned.  The trial
- * steps are real steps of the simulation (they advance the state and the step
- * count; inversion statistics become unavailable).  Synchronises the stream. */
+ * 96 persistent workgroups per XCD, in three rounds (one warm-up step before each
+ * timing); keep the shape with the fastest round and return it.  The trial steps
+ * (3 x candidates x (trial_steps + 1)) are real steps of the simulation (they
+ * advance the state and the step count; inversion statistics become unavailable).
+ * Synchronises the stream. */
 int rlbm_autotune(rlbm_ctx *ctx, int32_t trial_steps, int32_t *tile_x, int32_t *tile_y);
 
 /* rlbm_moments for grid g of a batch (g = 0 for a single grid). */

@@ -902,7 +902,9 @@ __device__ __forceinline__ void store_dev(void *fout, long long plane, int off, 
             smax = fmaxf(smax, fabsf(g[6 * n + k]));
         }
     }
-    const float inv = smax > 0.0f ? 1.0f / smax : 0.0f;
+    // hardware reciprocal (1 ulp): e stays within [-1, 1] up to that ulp, far below
+    // the half-precision step, and the decoder multiplies by smax itself
+    const float inv = smax > 0.0f ? __builtin_amdgcn_rcpf(smax) : 0.0f;
     const unsigned uoff = (unsigned)off;
 #pragma unroll
     for (int n = 0; n < 12; ++n) {
@@ -1612,31 +1614,44 @@ int rlbm_autotune(rlbm_ctx *c, int32_t trial_steps, int32_t *tile_x, int32_t *ti
         (void)hipEventDestroy(e0);
         return RLBM_EHIP;
     }
-    float best = 1e30f;
-    int bx = c->tx, by = c->ty, bp = c->persistent, rc = RLBM_OK;
-    for (const auto &t : cand) {
-        if (t[2] && !c->batch) continue;
-        c->persistent = t[2];
-        rc = configure(c, t[0], t[1]);
-        if (rc) break;
-        rc = launch_step(c, c->stream);   // warm-up
-        if (rc) break;
-        (void)hipEventRecord(e0, c->stream);
-        for (int i = 0; i < trial_steps && rc == RLBM_OK; ++i) rc = launch_step(c, c->stream);
-        (void)hipEventRecord(e1, c->stream);
-        if (rc || hipEventSynchronize(e1) != hipSuccess) {
-            rc = rc ? rc : RLBM_EHIP;
-            break;
-        }
-        float ms = 0.0f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        if (ms < best) {
-            best = ms;
-            bx = t[0];
-            by = t[1];
-            bp = t[2];
+    // three rounds over the candidates, each timed trial_steps steps after one
+    // warm-up step; a candidate's time is its best round (clock ramps and other
+    // transients only ever add time)
+    constexpr int NCAND = sizeof(cand) / sizeof(cand[0]), ROUNDS = 3;
+    float tmin[NCAND];
+    for (int i = 0; i < NCAND; ++i) tmin[i] = 1e30f;
+    int rc = RLBM_OK;
+    const int bx0 = c->tx, by0 = c->ty, bp0 = c->persistent;
+    for (int round = 0; round < ROUNDS && rc == RLBM_OK; ++round) {
+        for (int i = 0; i < NCAND && rc == RLBM_OK; ++i) {
+            const int *t = cand[i];
+            if (t[2] && !c->batch) continue;
+            c->persistent = t[2];
+            rc = configure(c, t[0], t[1]);
+            if (rc) break;
+            rc = launch_step(c, c->stream);   // warm-up
+            if (rc) break;
+            (void)hipEventRecord(e0, c->stream);
+            for (int k = 0; k < trial_steps && rc == RLBM_OK; ++k) rc = launch_step(c, c->stream);
+            (void)hipEventRecord(e1, c->stream);
+            if (rc || hipEventSynchronize(e1) != hipSuccess) {
+                rc = rc ? rc : RLBM_EHIP;
+                break;
+            }
+            float ms = 0.0f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            tmin[i] = fminf(tmin[i], ms);
         }
     }
+    int bx = bx0, by = by0, bp = bp0;
+    float best = 1e30f;
+    for (int i = 0; i < NCAND; ++i)
+        if (tmin[i] < best) {
+            best = tmin[i];
+            bx = cand[i][0];
+            by = cand[i][1];
+            bp = cand[i][2];
+        }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (c->p[0].collect_stats) c->stat_steps = -1;   // counters mixed with trial steps: invalid

@@ -167,11 +167,13 @@ def _grid_args(params, init, device, stream):
 class Sim:
     """One grid: owns two population tensors (ping-pong) on the current CUDA/HIP device.
 
-    params: dict with keys nx, ny, stats ('MJ'|'FD'|'BE'), precision ('fp64'|'fp32'),
-    tau_mode ('const'|'theta'), tau, tau_a, tau_b, bc (xlo, xhi, ylo, yhi names),
-    theta_wall (xlo, xhi), guess ('fixed'|'mlp'), tile ((tile_x, tile_y), default automatic),
-    force ((a_x, a_y), momentum update), wall_n and wall_theta (state imposed on 'wall_neq' sides).  init: dict of (ny, nx) float64
-    CUDA tensors theta, ux, uy and either n or z.
+    params: dict with keys nx, ny, stats ('MJ'|'FD'|'BE'), order (2..5, default 5),
+    precision ('fp64'|'fp32'|'f16dev'), tau_mode ('const'|'theta'), tau, tau_a, tau_b,
+    bc (xlo, xhi, ylo, yhi names from BC), theta_wall (xlo, xhi), guess ('fixed'|'mlp')
+    with mlp (the network's weight tensor), tile ((tile_x, tile_y), default automatic),
+    collect_stats, force ((a_x, a_y), momentum update), wall_n and wall_theta (state
+    imposed on 'wall_neq' sides).  init: dict of (ny, nx) float64 CUDA tensors theta,
+    ux, uy and either n or z.
     """
 
     def __init__(self, params, init, device="cuda", stream=None):
