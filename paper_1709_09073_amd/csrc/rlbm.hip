@@ -380,7 +380,7 @@ __device__ __forceinline__ void g_table(const double (*tab)[NG], int i, double d
     double t[K];
     t[0] = 1.0;
 #pragma unroll
-    for (int k = 1; k < K; ++k) t[k] = t[k - 1] * d * (1.0 / k);
+    for (int k = 1; k < K; ++k) t[k] = t[k - 1] * (d * (1.0 / k));   // d / k off the dependency chain
     const double *row = tab[i];
 #pragma unroll
     for (int m = MLO; m <= MHI; ++m) {
@@ -435,7 +435,7 @@ __device__ __forceinline__ void gvals(double mu, double (&g)[7], unsigned &flags
         double t[NZ];
         t[0] = 1.0;
 #pragma unroll
-        for (int k = 1; k < NZ; ++k) t[k] = t[k - 1] * mu * (1.0 / k);
+        for (int k = 1; k < NZ; ++k) t[k] = t[k - 1] * (mu * (1.0 / k));
 #pragma unroll
         for (int m = MLO; m <= MHI; ++m) {
             double s = 0;
@@ -444,6 +444,15 @@ __device__ __forceinline__ void gvals(double mu, double (&g)[7], unsigned &flags
             g[m] = s + t[m - 1] * (HARMONIC[m - 1] - L);
         }
     }
+}
+
+// 1/x from the hardware reciprocal estimate refined by two Newton-Raphson steps
+// (each squares the relative error): a short dependency chain without the scaling
+// steps of a correctly rounded division, for a positive normal x.
+__device__ __forceinline__ double rcp_refined(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(fma(-x, r, 1.0), r, r);
+    return fma(fma(-x, r, 1.0), r, r);
 }
 
 // Newton on mu = ln z leaves an error C dmu^2 after a step dmu, with C = f''/(2 f')
@@ -476,7 +485,7 @@ __device__ __forceinline__ double invert_h(double r, double mu, unsigned &flags,
         if constexpr (LOOSE) {
             // one FP64 division; the step itself only needs single precision: its
             // relative error (~1e-7) adds at most 1e-7 |dmu| to what the step leaves
-            const double a = 1.0 / (g[2] * g[3]);
+            const double a = rcp_refined(g[2] * g[3]);
             const double q = g[2] * g[2] * a;
             h = g[2] * q * q;
             const double D = h * (3.0 * g[1] * g[3] * a - 2.0 * q);

@@ -24,15 +24,18 @@ constexpr int NFLOAT = HDR + NTRAIN;
 static_assert(NFLOAT == RLBM_MLP_FLOATS, "weight layout");
 
 // mu = ln z guess from L = ln r (FP32 arithmetic; every lane reads the same weights)
+// The output sum runs in four interleaved partial sums (units h = 4i + j go to sum j)
+// so its dependency chain is a quarter as long.
 __device__ __forceinline__ float eval(const float *__restrict__ w, float L) {
+    static_assert(H % 4 == 0, "four partial sums");
     const float x = (L - w[0]) * w[1];
-    float y = w[HDR + 3 * H];
+    float y[4] = {w[HDR + 3 * H], 0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int h = 0; h < H; ++h) {
         const float z = w[HDR + h] * x + w[HDR + H + h];
-        y += w[HDR + 2 * H + h] * fmaxf(z, 0.0f);
+        y[h & 3] += w[HDR + 2 * H + h] * fmaxf(z, 0.0f);
     }
-    return w[2] + w[3] * y;
+    return w[2] + w[3] * ((y[0] + y[1]) + (y[2] + y[3]));
 }
 
 }  // namespace rlbm_mlp
