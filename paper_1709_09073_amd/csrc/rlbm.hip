@@ -483,7 +483,7 @@ __device__ __forceinline__ double invert_h(double r, double mu, unsigned &flags,
         gvals<ST, 1, 3, LOOSE>(mu, g, flags);
         double h, dmu;
         if constexpr (LOOSE) {
-            // one FP64 division; the step itself only needs single precision: its
+            // one FP64 reciprocal (1-2 ulp); the step itself only needs single precision: its
             // relative error (~1e-7) adds at most 1e-7 |dmu| to what the step leaves
             const double a = rcp_refined(g[2] * g[3]);
             const double q = g[2] * g[2] * a;
