@@ -1,9 +1,22 @@
-"""The constant tables compiled into the library are exactly what the generator
-writes: regenerating csrc/rlbm_tables.h (quadrature nodes and weights, separable
-projector, g_nu Taylor tables, zeta values) reproduces the committed header byte
-for byte, so no hand edit or stale table reaches the kernels."""
-import os
+"""The constant tables compiled into the library (csrc/rlbm_tables.h).
 
+* Regenerating them reproduces the committed header byte for byte, so no hand edit
+  or stale table reaches the kernels.
+* Their values agree with the oracle, which derives them by its own route
+  (Gram-Schmidt nodes, monomial-basis projector, vectorised g series), and the
+  separable equilibrium the kernels evaluate from them equals the oracle's
+  projection of the same state."""
+import math
+import os
+import re
+
+import mpmath as mp
+import numpy as np
+import pytest
+
+from oracle import equilibrium as OE
+from oracle import gfunc as OG
+from oracle import quadrature as OQ
 from paper_1709_09073_amd import gen_tables
 
 HEADER = os.path.join(os.path.dirname(gen_tables.__file__), "csrc", "rlbm_tables.h")
@@ -15,3 +28,87 @@ def test_generated_header_matches_committed(tmp_path):
     with open(HEADER) as fh:
         committed = fh.read()
     assert out.read_text() == committed
+
+
+# ---------------------------------------------------------------- table values
+STATS = ("MJ", "FD", "BE")
+
+
+def _tables():
+    text = open(HEADER).read()
+    out = {}
+    for m in re.finditer(r"(?:constexpr|__constant__) double (\w+)((?:\[\d+\])+) = \{(.*?)\};", text, re.S):
+        dims = [int(d) for d in re.findall(r"\[(\d+)\]", m.group(2))]
+        vals = [float(v) for v in re.findall(r"[-+]?(?:\d+\.?\d*(?:e[-+]?\d+)?|inf)", m.group(3))]
+        out[m.group(1)] = np.array(vals).reshape(dims)
+    for name in ("FD_MU_MIN", "FD_DMU", "BE_MU_MIN", "BE_DMU", "BE_MU_SPLIT"):
+        out[name] = float(re.search(name + r" = ([-\d.e+]+)", text).group(1))
+    return out
+
+
+T = _tables()
+
+
+@pytest.mark.parametrize("s", range(3))
+def test_quadrature_tables_match_oracle(s):
+    p, w = OQ.lattice(STATS[s])
+    np.testing.assert_allclose(T["P_SHELL"][s], p, rtol=4e-16, atol=0)
+    np.testing.assert_allclose(T["W_SHELL"][s], w, rtol=4e-16, atol=0)
+
+
+@pytest.mark.parametrize("stats", ["FD", "BE"])
+def test_g_taylor_centres_match_oracle(stats):
+    """Row i holds g_m(mu_c) for m = 6, 5, ..., at mu_c = MU_MIN + i DMU; the
+    positive orders are compared with the oracle's g series."""
+    tab = T[stats + "_TAB"]
+    mu = T[stats + "_MU_MIN"] + T[stats + "_DMU"] * np.arange(tab.shape[0])
+    for m in range(1, 7):
+        ref = OG.g_vec(stats, m, np.exp(mu))
+        np.testing.assert_allclose(tab[:, 6 - m], ref, rtol=2e-14, atol=0, err_msg=f"m={m}")
+
+
+def test_be_zeta_values():
+    """zeta(m) for m = 6 .. -23 with zeta(1) stored as 0 (mpmath, independent)."""
+    ref = [0.0 if m == 1 else float(mp.zeta(m)) for m in range(6, 6 - len(T["BE_ZETA"]), -1)]
+    np.testing.assert_allclose(T["BE_ZETA"], ref, rtol=1e-15, atol=1e-300)
+
+
+def _pair(j, k):
+    return j * 6 - (j * (j - 1)) // 2 + (k - j)
+
+
+def _feq_separable(s, theta, g, ux, uy, order):
+    """The kernels' separable route restated in NumPy: f^eq_{k,n} = sum_j r_j(k)
+    Re[(u_x + i u_y)^j e^{-i j phi_n}], r_j(k) = sum_{k'} E_{j k'}(k) G_{k'} P_{k'j}(u^2),
+    G_k' = k'! g_{k'+1} theta^{k'+1} gamma^{k'}."""
+    E = T["EMAT"][s] if order == 5 else T["EMAT_LO"][order - 2]
+    u2 = ux * ux + uy * uy
+    ga = 1.0 / math.sqrt(1.0 - u2)
+    G = [math.factorial(k) * g[k] * theta ** (k + 1) * ga ** k for k in range(6)]   # g[k] = g_{k+1}
+    phi = np.pi * np.arange(12) / 6
+    w = complex(ux, uy)
+    f = np.zeros((12, 6))
+    for j in range(order + 1):
+        A = np.real(w ** j * np.exp(-1j * j * phi))
+        for kk in range(j, order + 1):
+            P = T["PKJ"][_pair(j, kk)]
+            h = G[kk] * (P[0] + u2 * (P[1] + u2 * P[2]))
+            f += np.outer(A, E[_pair(j, kk)] * h)
+    return f.reshape(72)   # q = 6 n + k
+
+
+@pytest.mark.parametrize("stats,order", [("MJ", 5), ("FD", 5), ("BE", 5), ("MJ", 2), ("MJ", 3), ("MJ", 4)])
+def test_separable_equilibrium_matches_oracle_projection(stats, order):
+    """The projector tables in the separable form the kernels evaluate give the
+    oracle's monomial-basis projection of the same state."""
+    rng = np.random.default_rng(11)
+    s = STATS.index(stats)
+    for _ in range(6):
+        theta = rng.uniform(0.7, 1.4)
+        z = rng.uniform(0.3, 0.9) if stats == "BE" else rng.uniform(0.3, 2.0)
+        ux, uy = rng.uniform(-0.3, 0.3, 2)
+        g = OG.g_all(stats, np.array(z))
+        ref = OE.feq_lattice(stats, np.array(theta), g, np.array(ux), np.array(uy), order=order)
+        got = _feq_separable(s, theta, [float(x) for x in g], ux, uy, order)
+        err = np.abs(got - ref).max() / np.abs(ref).max()
+        assert err < 1e-12, (stats, order, err)
