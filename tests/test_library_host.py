@@ -12,6 +12,9 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 @pytest.fixture(scope="module")
 def rl():
     from paper_1709_09073_amd import rlbm
+    # test_sanitized_host.py reruns this module against an instrumented build
+    if os.environ.get("RLBM_TEST_LIBRARY"):
+        rlbm.LIB_PATH = os.environ["RLBM_TEST_LIBRARY"]
     rlbm.lib()
     return rlbm
 
