@@ -29,6 +29,8 @@ WORKLOADS = {
     "riemann_1024x4": "Riemann shock tube MJ 1024x4, n 1.0/0.139, theta = 1, tau = 0.9, x open, y periodic",
     "batched_sweep_64": "64 grids in one launch per step (seed 3): 32 Taylor-Green (L in 64..512 step 16, u0 = 0.05) "
                         "and 32 Fourier flows (walls theta 0.95/1.05, y periodic), tau ~ U[0.55, 1.5], MJ",
+    "poiseuille_2048": "forced flow between plates, MJ 2048x2049: acceleration 1e-8 along x, x periodic, "
+                       "non-equilibrium-extrapolation walls at y = 0 and 2048 (n = theta = 1), tau = 3",
 }
 
 
@@ -59,6 +61,9 @@ def build_workload(name, device):
         params, fields = workloads.hotspot_be(L=8192, device=device)
     elif name == "riemann_1024x4":
         params, fields = workloads.riemann(device=device)
+        params["stats"] = "MJ"
+    elif name == "poiseuille_2048":
+        params, fields = workloads.poiseuille(L=2048, nx=2048, a=1e-8, tau=3.0, device=device)
         params["stats"] = "MJ"
     elif name == "batched_sweep_64":
         return dict(nx=0, ny=0, stats="MJ"), {}
@@ -91,9 +96,10 @@ def recorded_traffic(workload, precision):
     return rec["traffic_bytes_per_launch"]
 
 
-def cpu_baseline(name, budget_s=15.0):
+def cpu_baseline(name, budget_s=15.0, order=5):
     """Time the FP64 oracle (as it stands) on a bounded sample: a 64 x 64 window of
-    the same workload's initial fields, as many steps as fit the budget."""
+    the same workload's initial fields (same order and forcing, open window edges),
+    as many steps as fit the budget."""
     import numpy as np
     try:
         import threadpoolctl
@@ -108,8 +114,9 @@ def cpu_baseline(name, budget_s=15.0):
     x0, y0 = (nx - w) // 2, (ny - h) // 2
     sub = {k: v[y0:y0 + h, x0:x0 + w].numpy() for k, v in fields.items()}
     bc = dict(zip(("xlo", "xhi", "ylo", "yhi"), ("open",) * 4))
-    op = L.Params(stats=params.get("stats", "MJ"), nx=w, ny=h, tau_mode=params.get("tau_mode", "const"),
-                  tau=params.get("tau", 1.0), tau_a=params.get("tau_a", 2.0), tau_b=params.get("tau_b", 0.2546), bc=bc)
+    op = L.Params(stats=params.get("stats", "MJ"), nx=w, ny=h, order=order, tau_mode=params.get("tau_mode", "const"),
+                  tau=params.get("tau", 1.0), tau_a=params.get("tau_a", 2.0), tau_b=params.get("tau_b", 0.2546), bc=bc,
+                  force=tuple(params.get("force", (0.0, 0.0))))
     f = L.init_state(op, sub["theta"], sub["ux"], sub["uy"], n=sub.get("n"), z=sub.get("z"))
     steps = 0
     t0, c0 = time.perf_counter(), time.process_time()
@@ -123,6 +130,24 @@ def cpu_baseline(name, budget_s=15.0):
     return dict(value=w * h * steps / dt / 1e6, unit="MLUPS", cores=used, kind="oracle",
                 sample=f"{w}x{h} window of the workload's initial fields, open boundaries, {steps} FP64 steps "
                        f"in {dt:.1f} s ({cpu / dt:.2f} cores busy on average, BLAS pool of {threads} threads)")
+
+
+def time_diagnostics(sim, ncell, cell_bytes, reps=5):
+    """Host-timed calls of the output kernels on the current state (each call
+    synchronises): the fields n, eps, theta, z, u, q (8 float64 outputs per cell) and
+    the non-equilibrium tensors of ranks 2-5 (4 float64 outputs per cell)."""
+    out = {}
+    for name, call, written in (("fields", lambda: sim.fields(), 64), ("noneq_tensors", lambda: sim.noneq_tensors(), 32)):
+        call()   # warm-up (output allocation)
+        best = float("inf")
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            call()
+            best = min(best, time.perf_counter() - t0)
+        nbytes = ncell * (cell_bytes + written)
+        out[name] = {"ms": round(best * 1e3, 4), "GB_per_s": round(nbytes / best / 1e9, 1),
+                     "bytes_per_call": nbytes, "note": "best of %d host-timed calls, sync included" % reps}
+    return out
 
 
 def train_guess_net(name, device, iters=3000):
@@ -236,6 +261,10 @@ def main():
     ap.add_argument("--guess-iters", type=int, default=3000, help="Adam steps when training the guess network")
     ap.add_argument("--guess", default="mlp", choices=["fixed", "mlp"],
                     help="FD/BE inversion start: fixed, or the network trained on a smaller run first")
+    ap.add_argument("--order", type=int, default=5, choices=[2, 3, 4, 5],
+                    help="expansion order of the equilibrium (2-4: Maxwell-Juttner workloads)")
+    ap.add_argument("--diagnostics", action="store_true",
+                    help="also time the field (n, eps, theta, z, u, q) and non-equilibrium tensor kernels")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path", file=sys.stderr)
@@ -247,6 +276,7 @@ def main():
     dev = "cuda"
     params, fields = build_workload(args.workload, dev)
     params["precision"] = args.precision
+    params["order"] = args.order
     if args.tile != "auto":
         params["tile"] = tuple(int(v) for v in args.tile.split("x"))
     print(f"[bench] workload={args.workload} precision={args.precision} grid={params['nx']}x{params['ny']} "
@@ -283,6 +313,7 @@ def main():
     bytes_per_launch = 2 * cell_bytes * ncell
     launch_s = ms * 1e-3 / args.steps
     achieved = bytes_per_launch / launch_s / 1e9
+    diag = time_diagnostics(sim, ncell, cell_bytes) if args.diagnostics and "grids" not in params else None
     sim.close()
     print(f"[bench] {mlups:.1f} MLUPS, {achieved:.0f} GB/s, status=0x{status:x}", file=sys.stderr, flush=True)
 
@@ -302,14 +333,16 @@ def main():
         "config": {"workload": args.workload, "description": WORKLOADS[args.workload],
                    "grid": [params["nx"], params["ny"]] if "grids" not in params else None,
                    "grids": params.get("grids", 1), "cells": ncell, "statistic": params.get("stats", "MJ"),
-                   "order": 5, "lattice": "d2v72", "populations": args.precision, "inversion_guess": args.guess, "guess_net": net_info, "tile": args.tile,
+                   "order": args.order, "lattice": "d2v72", "populations": args.precision, "inversion_guess": args.guess, "guess_net": net_info, "tile": args.tile,
                    "status_bits": status},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": recorded_traffic(args.workload, args.precision),
                      "algorithmic_bytes_per_launch": bytes_per_launch, "kernel": "k_step"},
     }
-    if not args.no_variants and args.workload in ("fd_hotspot_2048", "be_hotspot_8192"):
+    if diag is not None:
+        out["diagnostics"] = diag
+    if not args.no_variants and args.order == 5 and args.workload in ("fd_hotspot_2048", "be_hotspot_8192"):
         vsteps = max(100, min(args.steps, 500))
         out["variants"] = {"unit": "MLUPS", "steps": vsteps, **variants(args.workload, net, vsteps)}
         out["error_vs_fp64"] = error_vs_fp64(args.workload)
@@ -321,7 +354,7 @@ def main():
                                        "reduced_eps_theta": e["f16dev"]["eps_theta"],
                                        "reduced_eps_q": e["f16dev"]["eps_q"], "error_bar": 1e-3}
     if not args.no_cpu_baseline and args.workload != "batched_sweep_64":
-        out["cpu_baseline"] = cpu_baseline(args.workload)
+        out["cpu_baseline"] = cpu_baseline(args.workload, order=args.order)
     print(json.dumps(out), flush=True)
 
 
