@@ -29,8 +29,10 @@
  *  - Field arrays are double, nx*ny elements, row-major [y][x].
  *  - Ownership: the caller allocates every population and field buffer in
  *    device memory and keeps it alive until rlbm_free.  The library allocates
- *    only a small status word per context.  No pointer passed in is freed by
- *    the library.
+ *    only small per-context device memory (status word, two counters, and for a
+ *    batch its descriptor tables) plus the captured graphs; the network calls use
+ *    a workspace the caller provides.  No pointer passed in is freed by the
+ *    library.
  *  - Errors: every int-returning call returns RLBM_OK (0) or a negative code;
  *    rlbm_strerror gives its text.  No C++ exception crosses this interface.
  *    Domain failures found inside kernels (non-positive n or eps, |u| >= 1,
@@ -134,7 +136,8 @@ int rlbm_init(rlbm_ctx **ctx, const rlbm_params *p, const rlbm_init_fields *init
 /* Several independent grids of uneven sizes in one context: p[g] and init[g] for
  * g < ngrids, each with its own shape, relaxation time, boundaries and buffers;
  * stats, precision, order, guess, mlp, stream, tile and collect_stats must agree.
- * Every step advances all grids with one persistent launch over all their tiles.
+ * Every step advances all grids with one launch over all their tiles (one
+ * workgroup per tile, or a persistent sweep: rlbm_configure, rlbm_autotune).
  * Intended for transport-coefficient sweeps.  Errors as rlbm_init. */
 int rlbm_init_batch(rlbm_ctx **ctx, int32_t ngrids, const rlbm_params *p, const rlbm_init_fields *init);
 
