@@ -5,7 +5,8 @@ Bars are relative to the per-cell scale sum_i |f_i| |p_i^x|^r, the size of the t
 sums whose difference pi is.  FP64 populations: 2e-13 for every rank after 6 steps
 (each sum carries ~1e-15 relative rounding per step on either side; the errors seen
 stay below 2.5e-14).  FP32 populations: 2e-6 for every rank (storage rounding 2^-24
-per step plus the FP32 equilibrium synthesis; seen: below 5e-7)."""
+per step plus the FP32 equilibrium synthesis; seen: below 5e-7).  FP16 deviations:
+the same bar against the oracle run on the decoded GPU state."""
 import numpy as np
 import pytest
 import torch
@@ -67,7 +68,32 @@ def test_lower_orders_fp64(rl, order):
     _check(got, ref, scale, BAR_FP64, f"MJ N={order} fp64")
 
 
-@pytest.mark.parametrize("stats", ["MJ", "FD"])
+@pytest.mark.parametrize("stats", ["MJ", "FD", "BE"])
 def test_fifth_order_fp32(rl, stats):
     got, ref, scale = _case(rl, stats, "fp32", 5, 6)
     _check(got, ref, scale, BAR_FP32, f"{stats} N=5 fp32")
+
+
+@pytest.mark.parametrize("stats", ["MJ", "FD", "BE"])
+def test_fifth_order_f16dev(rl, stats):
+    """FP16-deviation storage: the oracle takes the GPU's stored state, decoded
+    exactly on the host (f_i = w_k (R_i + s e_i)), so both sides see the same
+    populations and the FP32 bar applies (the GPU decodes and interpolates in FP32)."""
+    nx, ny, steps = 40, 24, 6
+    fields = workloads.smooth_random(nx, ny, 23, stats=stats, amp_theta=0.2, amp_u=0.2)
+    params = dict(nx=nx, ny=ny, stats=stats, precision="f16dev", tau_mode="const", tau=0.8, bc=("periodic",) * 4)
+    sim = rl.Sim(params, {k: v.cuda() for k, v in fields.items()})
+    sim.step(steps)
+    got = {r: v.cpu().numpy() for r, v in sim.noneq_tensors().items()}
+    dev, side = rl.f16dev_views(sim.state(), nx, ny)
+    sim.close()
+    e = dev.double().cpu().numpy()
+    sd = side.double().cpu().numpy()
+    v = Q.vectors(stats)
+    R = sd[v["k"]] + v["p0"][:, None, None] * (sd[6] * v["vx"][:, None, None] + sd[7] * v["vy"][:, None, None])
+    f = v["w"][:, None, None] * (R + sd[8] * e)
+    op = L.Params(stats=stats, nx=nx, ny=ny, tau=0.8)
+    ref = L.noneq_tensors(f, op)
+    fs = L.stream(f, op)
+    scale = {r: np.tensordot(np.abs(v["px"]) ** r, np.abs(fs), axes=(0, 0)) for r in ref}
+    _check(got, ref, scale, BAR_FP32, f"{stats} N=5 f16dev")

@@ -44,6 +44,29 @@ def test_lower_order_parity(rl, order, bc):
         assert err <= 5e-12, (key, err)
 
 
+@pytest.mark.parametrize("order", [2, 3, 4])
+def test_lower_order_walls(rl, order):
+    """Fixed-temperature x walls (Sec. 3.3) set the order-N equilibrium."""
+    nx, ny, nsteps = 37, 8, 5
+    fields = workloads.smooth_random(nx, ny, seed=10 + order, stats="MJ", amp_u=0.1)
+    tw = (0.95, 1.08)
+    bc = ("wall", "wall", "periodic", "periodic")
+    print(f"[orders] N={order} walls {nx}x{ny} {nsteps} steps", flush=True)
+    sim = rl.Sim(dict(nx=nx, ny=ny, stats="MJ", precision="fp64", order=order, tau=0.9, bc=bc, theta_wall=tw),
+                 {k: v.cuda() for k, v in fields.items()})
+    sim.step(nsteps)
+    pops = sim.populations().cpu().numpy()
+    sim.close()
+    op = L.Params(stats="MJ", nx=nx, ny=ny, order=order, tau=0.9, bc=dict(zip(("xlo", "xhi", "ylo", "yhi"), bc)),
+                  theta_wall=dict(xlo=tw[0], xhi=tw[1]))
+    f = L.init_state(op, fields["theta"].numpy(), fields["ux"].numpy(), fields["uy"].numpy(), z=fields["z"].numpy())
+    for _ in range(nsteps):
+        f, _ = L.step(f, op)
+    for k in range(6):
+        sl = slice(k, 72, 6)
+        assert np.abs(pops[sl] - f[sl]).max() <= 2e-11 * np.abs(f[sl]).max(), k
+
+
 def test_hotspot_order_deviations(rl):
     """eps_theta^(N), eps_q^(N) of orders 2-4 against order 5 at t = 100, FP64, against
     the values printed in Sec. 3.5.  Measured here: heat-flux deviations of orders 2

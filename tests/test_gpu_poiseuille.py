@@ -70,16 +70,17 @@ def test_forced_walls_parity_fp64(rl, stats):
         assert err <= VEL_TOL_FP64, (key, err)
 
 
-def test_forced_walls_parity_fp32(rl):
+@pytest.mark.parametrize("stats", ["MJ", "FD", "BE"])
+def test_forced_walls_parity_fp32(rl, stats):
     nx, ny, steps = 12, 11, 6
     params, _ = workloads.poiseuille(L=ny - 1, nx=nx, a=2e-3, tau=1.1)
-    params = dict(params, stats="FD", precision="fp32")
-    fields = workloads.smooth_random(nx, ny, seed=14, stats="FD", amp_u=0.1)
+    params = dict(params, stats=stats, precision="fp32")
+    fields = workloads.smooth_random(nx, ny, seed=14, stats=stats, amp_u=0.1)
     sim = rl.Sim(params, {k: v.cuda() for k, v in fields.items()})
     sim.step(steps)
     got = {k: v.cpu().numpy() for k, v in sim.fields().items()}
     sim.close()
-    op = _oracle_params(params, "FD")
+    op = _oracle_params(params, stats)
     f0 = {k: v.numpy() for k, v in fields.items()}
     ref = L.fields(L.run(L.init_state(op, f0["theta"], f0["ux"], f0["uy"], z=f0["z"]), op, steps), op)
     for key, tol in dict(n=2e-6, eps=2e-6, theta=2e-6, z=5e-6).items():
