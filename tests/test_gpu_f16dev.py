@@ -32,17 +32,27 @@ def decode(rl, buf, nx, ny, stats):
     return v["w"][:, None, None] * (R + sd[8] * e)
 
 
-@pytest.mark.parametrize("stats,nsteps", [("MJ", 6), ("FD", 4), ("BE", 4)])
-def test_f16dev_against_oracle(rl, stats, nsteps):
+WALLS = dict(bc=("wall", "wall", "open", "open"), theta_wall=(0.93, 1.06), tau_mode="theta", tau_a=0.5, tau_b=0.6)
+
+
+@pytest.mark.parametrize("stats,nsteps,setup", [("MJ", 6, "periodic"), ("FD", 4, "periodic"), ("BE", 4, "periodic"),
+                                                ("MJ", 5, "walls"), ("FD", 4, "walls"), ("BE", 4, "walls")])
+def test_f16dev_against_oracle(rl, stats, nsteps, setup):
     nx, ny = 70, 13
     fields = workloads.smooth_random(nx, ny, seed=31, stats=stats)
-    print(f"[f16dev] {stats} {nx}x{ny} {nsteps} steps vs oracle", flush=True)
-    sim = rl.Sim(dict(nx=nx, ny=ny, stats=stats, precision="f16dev", tau=0.9),
+    extra = WALLS if setup == "walls" else {}
+    print(f"[f16dev] {stats} {nx}x{ny} {setup} {nsteps} steps vs oracle", flush=True)
+    sim = rl.Sim(dict(nx=nx, ny=ny, stats=stats, precision="f16dev", tau=0.9, **extra),
                  {k: v.cuda() for k, v in fields.items()})
     # the initial state decodes to the equilibrium within the half-precision rounding
     # of the scaled deviation: |f - f_eq| <= w_k s 2^-11 (plus FP32 rounding of f_eq)
     f0 = decode(rl, sim.state(), nx, ny, stats)
-    op = L.Params(stats=stats, nx=nx, ny=ny, tau=0.9)
+    if setup == "walls":
+        op = L.Params(stats=stats, nx=nx, ny=ny, tau_mode="theta", tau_a=0.5, tau_b=0.6,
+                      bc=dict(zip(("xlo", "xhi", "ylo", "yhi"), WALLS["bc"])),
+                      theta_wall=dict(xlo=WALLS["theta_wall"][0], xhi=WALLS["theta_wall"][1]))
+    else:
+        op = L.Params(stats=stats, nx=nx, ny=ny, tau=0.9)
     ref0 = L.init_state(op, fields["theta"].numpy(), fields["ux"].numpy(), fields["uy"].numpy(), z=fields["z"].numpy())
     _, side = rl.f16dev_views(sim.state(), nx, ny)
     s = side[8].double().cpu().numpy()
