@@ -64,3 +64,23 @@ def test_directions_are_exact():
         for n in range(12):
             assert abs(Q.COS_DIR[n] - float(mp.cos(mp.pi * n / 6))) < 1e-16
             assert abs(Q.SIN_DIR[n] - float(mp.sin(mp.pi * n / 6))) < 1e-16
+
+
+@pytest.mark.parametrize("stats", Q.STATS)
+def test_radial_moments_by_direct_integration(stats):
+    """mu_k = int_0^inf omega(p) p^k dp for k = 0..12 (the moments the radial rule is
+    built from) against direct numerical integration of the weight functions of
+    Eqs. mj-w-eq, fd-w-eq and be-w-eq, not through their closed forms (factorials,
+    the eta function, the polylogarithm)."""
+    zc = Q.Z_C_BE
+    with mp.workdps(40):
+        weight = {"MJ": lambda p: mp.exp(-p) / (2 * mp.pi),
+                  "FD": lambda p: 1 / (mp.exp(p) + 1),
+                  "BE": lambda p: 1 / (mp.exp(p) / zc - 1)}[stats]
+        # the BE weight peaks like 1/(p + 1e-7) at the origin: split the range there
+        pts = [0, mp.mpf(10) ** -9, mp.mpf(10) ** -7, mp.mpf(10) ** -5, mp.mpf(10) ** -3, mp.mpf("0.1"), 1, 4, 10,
+               25, 60, 150, mp.inf]
+        for k in range(13):
+            direct = mp.quad(lambda p: weight(p) * p ** k, pts)
+            mu = Q.radial_moment(stats, k)
+            assert abs(mu / direct - 1) < mp.mpf(10) ** -20, (stats, k, mu, direct)
