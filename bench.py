@@ -28,7 +28,7 @@ WORKLOADS = {
     "be_hotspot_8192": "Bose-Einstein 8192x8192, 16 seeded Gaussian theta/fugacity bumps, tau = 2/theta + 0.2546, open",
     "riemann_1024x4": "Riemann shock tube MJ 1024x4, n 1.0/0.139, theta = 1, tau = 0.9, x open, y periodic",
     "batched_sweep_64": "64 grids in one launch per step (seed 3): 32 Taylor-Green (L in 64..512 step 16, u0 = 0.05) "
-                        "and 32 Fourier flows (walls theta 0.95/1.05, y periodic), tau ~ U[0.55, 1.5], MJ",
+                        "and 32 Fourier flows (walls theta 1 -/+ 5e-4, y periodic), tau ~ U[0.55, 1.5], MJ",
     "poiseuille_2048": "forced flow between plates, MJ 2048x2049: acceleration 1e-8 along x, x periodic, "
                        "non-equilibrium-extrapolation walls at y = 0 and 2048 (n = theta = 1), tau = 3",
 }
@@ -248,6 +248,19 @@ def error_vs_fp64(name, steps=400, L=256):
     return out
 
 
+def copy_calibration(nbytes=1 << 30, reps=3):
+    """A plain device copy of a known size (nbytes, reps times), run under
+    rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE to calibrate those counters: the counter per
+    copy dispatch divided into nbytes is the scale applied to the step kernel's."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(f"[bench] copied {nbytes} bytes {reps} times", file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -265,7 +278,12 @@ def main():
                     help="expansion order of the equilibrium (2-4: Maxwell-Juttner workloads)")
     ap.add_argument("--diagnostics", action="store_true",
                     help="also time the field (n, eps, theta, z, u, q) and non-equilibrium tensor kernels")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device copy three times (HBM counter calibration) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path", file=sys.stderr)
         raise SystemExit(2)

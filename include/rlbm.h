@@ -83,11 +83,14 @@ enum rlbm_bc {
 enum rlbm_guess { RLBM_GUESS_FIXED = 0, RLBM_GUESS_MLP = 1 };       /* FD/BE inversion start */
 
 /* status-word bits (rlbm_status) */
-#define RLBM_FLAG_NONPOSITIVE  0x1u  /* n <= 0, eps <= 0 or a non-finite moment */
+#define RLBM_FLAG_NONPOSITIVE  0x1u  /* n <= 0 or eps <= 0 */
 #define RLBM_FLAG_SUPERLUMINAL 0x2u  /* |u| >= 1 */
 #define RLBM_FLAG_CONDENSED    0x4u  /* BE: 2n^3/(pi eps^2) >= h(z_c); z clamped to z_c */
 #define RLBM_FLAG_RANGE        0x8u  /* FD: ln z above the table range (12.125) */
 #define RLBM_FLAG_NOCONV       0x10u /* Landau or inversion iteration hit its limit */
+#define RLBM_FLAG_NONFINITE    0x20u /* a non-finite moment (NaN or infinite population) */
+#define RLBM_FLAG_UNSTABLE     0x40u /* init: tau <= gamma (1 + |u|) / 2 in some cell, where the largest
+                                        Anderson-Witting weight gamma (1 - v.u) / tau reaches 2 */
 
 typedef struct rlbm_params {
     int32_t nx, ny;          /* grid size, both >= 2 (walls need nx >= 4) */
@@ -96,7 +99,7 @@ typedef struct rlbm_params {
                                 for Maxwell-Juttner with FP64/FP32 populations on single grids */
     int32_t precision;       /* rlbm_precision: element type of f_a, f_b */
     int32_t tau_mode;        /* rlbm_tau_mode */
-    double tau;              /* constant relaxation time (> 0.5 recommended) */
+    double tau;              /* constant relaxation time, > 0.5 (see rlbm_init for the per-cell bound) */
     double tau_a, tau_b;     /* tau = tau_a / theta + tau_b (Sec. 3.2: 4 eta/s, 0.2546) */
     int32_t bc[4];           /* sides x-low, x-high, y-low, y-high: rlbm_bc */
     double theta_wall[2];    /* wall temperature of the x-low and x-high sides */
@@ -112,6 +115,8 @@ typedef struct rlbm_params {
     double force[2];         /* constant acceleration (a_x, a_y) applied by momentum update: the
                                 collision uses u + a tau (Sec. 3.4); 0, 0 = none */
     double wall_n, wall_theta; /* imposed density and temperature of RLBM_BC_WALL_NEQ sides */
+    int32_t check;           /* 1: check mode, every rlbm_step call waits for its steps and returns
+                                the status word's verdict (RLBM_ENONFINITE, RLBM_EDOMAIN); 0: asynchronous */
 } rlbm_params;
 
 typedef struct rlbm_init_fields {
@@ -123,17 +128,26 @@ typedef struct rlbm_init_fields {
 typedef struct rlbm_out_fields {
     /* device pointers, nx*ny doubles each; a NULL entry is not written */
     double *n, *eps, *theta, *z, *ux, *uy, *qx, *qy;
+    /* optional raw moments of the same populations (Sec. 2.4, Eq. density-eq): the particle
+       current N^mu = sum_i f_i p_i^mu and the energy-momentum tensor T^{mu nu} =
+       sum_i f_i p_i^mu p_i^nu (symmetric, traceless: T^00 = T^xx + T^yy) */
+    double *N0, *Nx, *Ny, *T00, *T0x, *T0y, *Txx, *Txy, *Tyy;
 } rlbm_out_fields;
 
 typedef struct rlbm_ctx rlbm_ctx;
 
 /* Validate p, build a context and write the initial state f* = f^eq(fields)
- * into f_a (Eq. expansion-eq; for FD/BE with n given, z solves
- * n = 2 pi theta^2 g_2(z), Eq. n-eps-eq).  On success *ctx owns a status word;
- * on failure *ctx is NULL.  Errors: RLBM_EINVAL, RLBM_EHIP. */
+ * into f_a: the equilibrium of Eq. expansion-eq on the quadrature of Sec. 2.4; for
+ * FD/BE with n given, z solves n = 2 pi theta^2 g_2(z) (Eq. n-eps-eq).  Synchronises
+ * the stream.  On success *ctx owns a status word; on failure *ctx is NULL.
+ * Errors: RLBM_EINVAL (bad parameters, or a cell where tau <= gamma (1 + |u|)/2: the
+ * Anderson-Witting weight gamma (1 - v.u)/tau of Sec. 2.1 would reach 2 there, an
+ * over-relaxation the update does not survive), RLBM_EHIP.  Domain flags raised while
+ * building the state (e.g. a BE density above condensation) stay in the status word. */
 int rlbm_init(rlbm_ctx **ctx, const rlbm_params *p, const rlbm_init_fields *init);
 
-/* Several independent grids of uneven sizes in one context: p[g] and init[g] for
+/* Several independent grids of uneven sizes in one context (project extension for
+ * the transport sweeps of Sec. 3.2 and Sec. 3.3): p[g] and init[g] for
  * g < ngrids, each with its own shape, relaxation time, boundaries and buffers;
  * stats, precision, order, guess, mlp, stream, tile and collect_stats must agree.
  * Every step advances all grids with one launch over all their tiles (one
@@ -141,40 +155,51 @@ int rlbm_init(rlbm_ctx **ctx, const rlbm_params *p, const rlbm_init_fields *init
  * Intended for transport-coefficient sweeps.  Errors as rlbm_init. */
 int rlbm_init_batch(rlbm_ctx **ctx, int32_t ngrids, const rlbm_params *p, const rlbm_init_fields *init);
 
-/* Enqueue nsteps >= 0 time steps (ping-pong between f_a and f_b of every grid).
+/* Enqueue nsteps >= 0 time steps (ping-pong between f_a and f_b of every grid).  A
+ * step is the discrete Anderson-Witting update of Sec. 2.1 with the pull streaming of
+ * Sec. 2.4: moments, Landau frame (Eq. eigen-eq), density (Eq. density-eq), inversion
+ * (Eqs. theta-eq, n-eps-eq, gz-eq), relaxation time (Sec. 3.2), equilibrium (Eq.
+ * expansion-eq), relaxation; the order is spelled out at the top of this file.
  * Runs of 64 or more steps replay captured graphs of 32 steps (one graph launch
- * per 32 steps).  Errors: RLBM_EINVAL (nsteps < 0 or ctx NULL), RLBM_EHIP. */
+ * per 32 steps).  Asynchronous, except in check mode (rlbm_params.check = 1), where
+ * the call waits for its steps and returns as rlbm_sync.  Errors: RLBM_EINVAL (nsteps
+ * < 0 or ctx NULL), RLBM_EHIP; in check mode also RLBM_ENONFINITE, RLBM_EDOMAIN. */
 int rlbm_step(rlbm_ctx *ctx, int64_t nsteps);
 
 /* Capture the 32-step graphs that rlbm_step replays (for both parities) now, so
- * that a later timed run does not include capture and instantiation.  Runs no step. */
+ * that a later timed run does not include capture and instantiation.  Runs no step.
+ * (Project extension: scheduling of the update of Sec. 2.1, not part of the method.) */
 int rlbm_capture(rlbm_ctx *ctx);
 
-/* Set the workgroup tile (tile_x * tile_y = 256, tile_x a power of two >= 16) and,
+/* (Project extension; scheduling only, results do not depend on it.)
+ * Set the workgroup tile (tile_x * tile_y = 256, tile_x a power of two >= 16) and,
  * for a batch, the launch mode: persistent > 0 launches that many workgroups per
  * XCD, each sweeping tiles of its XCD's range; 0 launches one workgroup per tile.
  * Drops captured graphs.  Errors: RLBM_EINVAL, RLBM_EHIP. */
 int rlbm_configure(rlbm_ctx *ctx, int32_t tile_x, int32_t tile_y, int32_t persistent);
 
-/* Time trial_steps steps with each workgroup tile shape in {32x8, 64x4, 16x16,
+/* (Project extension; scheduling only.)
+ * Time trial_steps steps with each workgroup tile shape in {32x8, 64x4, 16x16,
  * 128x2, 256x1} (one workgroup per tile) and, for a batch, also 32x8 and 64x4 with
  * 96 persistent workgroups per XCD, in three rounds (one warm-up step before each
  * timing); keep the shape with the fastest round and return it.  The trial steps
  * (3 x candidates x (trial_steps + 1)) are real steps of the simulation (they
- * advance the state and the step count; inversion statistics become unavailable).
- * Synchronises the stream. */
+ * advance the state and the step count); the inversion counters restart from zero
+ * after the trials.  Synchronises the stream. */
 int rlbm_autotune(rlbm_ctx *ctx, int32_t trial_steps, int32_t *tile_x, int32_t *tile_y);
 
 /* rlbm_moments for grid g of a batch (g = 0 for a single grid). */
 int rlbm_moments_grid(rlbm_ctx *ctx, int32_t g, const rlbm_out_fields *out);
 
 /* Fields of the current state (moments of the pre-collision populations the next
- * step would see), written to the non-NULL device arrays of out; synchronises the
- * stream.  Returns RLBM_EDOMAIN if the status word has bits set (then clears it). */
+ * step would see), written to the non-NULL device arrays of out: n (Eq. density-eq),
+ * eps and u (Eq. eigen-eq), theta and z (Eqs. theta-eq, n-eps-eq), q (Eq. heat-eq2),
+ * and the raw moments N^mu, T^{mu nu} (Sec. 2.4).  Synchronises the stream.  Returns
+ * as rlbm_sync (the status word includes what this call's own kernel raised). */
 int rlbm_moments(rlbm_ctx *ctx, const rlbm_out_fields *out);
 
 /* Diagonal x components of the non-equilibrium tensors of ranks 2 to 5 (Eq.
- * tensors-eq), pi^{x..x} = sum_i (f_i - f^eq_i) (p_i^x)^r, of grid g's current state:
+ * tensors-eq, Sec. 3.1), pi^{x..x} = sum_i (f_i - f^eq_i) (p_i^x)^r, of grid g's current state:
  * f are the pre-collision populations the next step would see and f^eq the
  * equilibrium of the expansion order in use at the cell's own (theta, z, u).
  * Outputs are device arrays of nx*ny doubles (y-major); a NULL one is skipped.
@@ -182,26 +207,30 @@ int rlbm_moments(rlbm_ctx *ctx, const rlbm_out_fields *out);
 int rlbm_noneq_tensors(rlbm_ctx *ctx, int32_t g, double *pi_xx, double *pi_xxx, double *pi_xxxx,
                        double *pi_xxxxx);
 
-/* 0 if f_a holds the current state, 1 if f_b does. */
+/* 0 if f_a holds the current state, 1 if f_b does (the stored state is the
+ * post-collision population of Sec. 2.1's update). */
 int rlbm_state_index(const rlbm_ctx *ctx);
 
 /* Number of steps taken since rlbm_init. */
 int64_t rlbm_steps_done(const rlbm_ctx *ctx);
 
-/* Wait for the stream; RLBM_EDOMAIN if the status word is non-zero (then cleared). */
+/* Wait for the stream and report the status word, then clear it: RLBM_ENONFINITE if
+ * RLBM_FLAG_NONFINITE is set, else RLBM_EDOMAIN if any bit is set, else RLBM_OK. */
 int rlbm_sync(rlbm_ctx *ctx);
 
 /* Wait for the stream and return the status-word bits without clearing them. */
 uint32_t rlbm_status(rlbm_ctx *ctx);
 
-/* Newton iterations and solves of the FD/BE (n, eps) -> (theta, z) inversion summed
- * over all step launches since rlbm_init (collect_stats = 1; otherwise zeros).
- * Synchronises the stream.  Errors: RLBM_EINVAL, RLBM_EHIP. */
+/* Newton iterations and solves of the FD/BE (n, eps) -> (theta, z) inversion (Eqs.
+ * n-eps-eq, gz-eq) summed over all step launches since rlbm_init or since the last
+ * rlbm_autotune (collect_stats = 1; otherwise zeros).  Synchronises the stream.
+ * Errors: RLBM_EINVAL, RLBM_EHIP. */
 int rlbm_inversion_stats(rlbm_ctx *ctx, uint64_t *iterations, uint64_t *solves);
 
 /* Training pairs from the current state, one per cell (FP32 device arrays of
- * nx*ny): x = ln r with r = 2 n^3 / (pi eps^2), t = ln z, from the same moments,
- * Landau frame and inversion as rlbm_moments.  Synchronises the stream. */
+ * nx*ny): x = ln r with r = 2 n^3 / (pi eps^2), t = ln z (the one-dimensional form of
+ * Eq. n-eps-eq, theta cancelling), from the same moments, Landau frame and inversion
+ * as rlbm_moments.  Synchronises the stream; returns as rlbm_sync. */
 int rlbm_inversion_samples(rlbm_ctx *ctx, float *x, float *t);
 
 /* ---- the inversion-guess network (project extension, not in the paper) -------

@@ -102,6 +102,7 @@ struct KArgs {
     // field outputs
     double *o_n, *o_eps, *o_theta, *o_z, *o_ux, *o_uy, *o_qx, *o_qy;
     double *o_pi[4];             // non-equilibrium tensors pi^{x..x} of rank 2..5
+    double *o_mom[9];            // raw moments N^0, N^x, N^y, T^00, T^0x, T^0y, T^xx, T^xy, T^yy
 };
 
 // ---------------------------------------------------------------- tile mapping
@@ -566,10 +567,12 @@ __device__ __forceinline__ void state_from_moments(const Mom &m, Macro &M, unsig
     }
     M.ga = 1.0 / sqrt(1.0 - (M.ux * M.ux + M.uy * M.uy));
     M.n = M.ga * (m.N0 - M.ux * m.Nx - M.uy * m.Ny);
-    if (!(M.n > 0.0) || !(M.eps > 0.0)) {
-        flags |= RLBM_FLAG_NONPOSITIVE;
-        M.n = M.n > 0.0 ? M.n : 1.0;
-        M.eps = M.eps > 0.0 ? M.eps : 1.0;
+    // a NaN or infinite population makes N^0 and T^00 (every p^0 > 0) and so n or eps
+    // non-finite; comparisons with NaN are false
+    if (!(M.n > 0.0 && M.n < INFINITY) || !(M.eps > 0.0 && M.eps < INFINITY)) {
+        flags |= (fabs(M.n) < INFINITY && fabs(M.eps) < INFINITY) ? RLBM_FLAG_NONPOSITIVE : RLBM_FLAG_NONFINITE;
+        M.n = (M.n > 0.0 && M.n < INFINITY) ? M.n : 1.0;
+        M.eps = (M.eps > 0.0 && M.eps < INFINITY) ? M.eps : 1.0;
     }
     const double r = 2.0 * M.n * M.n * M.n / (PI_D * M.eps * M.eps);
     if (L_out) *L_out = log(r);
@@ -1094,6 +1097,10 @@ __global__ __launch_bounds__(256) void k_moments(KArgs a) {
     if (a.o_uy) a.o_uy[off] = M.uy;
     if (a.o_qx) a.o_qx[off] = hE * (M.n * M.ga * M.ux - m.Nx);
     if (a.o_qy) a.o_qy[off] = hE * (M.n * M.ga * M.uy - m.Ny);
+    const double raw[9] = {m.N0, m.Nx, m.Ny, m.T00, m.T01, m.T02, m.T11, m.T12, m.T22};
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+        if (a.o_mom[i]) a.o_mom[i][off] = raw[i];
     report(a.status, flags);
 }
 
@@ -1166,6 +1173,10 @@ __global__ __launch_bounds__(256) void k_init(KArgs a) {
     }
     M.ga = 1.0 / sqrt(1.0 - (M.ux * M.ux + M.uy * M.uy));
     const double th = a.i_theta[off];
+    // the largest Anderson-Witting weight gamma (1 - v.u)/tau over the directions is
+    // gamma (1 + |u|)/tau; from 2 on the relaxation over-shoots without bound
+    const double tau = (a.tau_mode == RLBM_TAU_CONST) ? a.tau : a.tau_a / th + a.tau_b;
+    if (!(tau > 0.5 * M.ga * (1.0 + sqrt(M.ux * M.ux + M.uy * M.uy)))) flags |= RLBM_FLAG_UNSTABLE;
     if (a.given_z) state_from_z_theta<ST>(a.i_z[off], th, M, flags);
     else state_from_n_theta<ST>(a.i_n[off], th, M, flags);
     R f[72];
@@ -1301,7 +1312,7 @@ int validate(const rlbm_params *p) {
         return RLBM_ENOTIMPL;   // lower orders: Maxwell-Juttner with FP64 or FP32 populations
     if (p->precision != RLBM_FP64 && p->precision != RLBM_FP32 && p->precision != RLBM_F16DEV) return RLBM_EINVAL;
     if (p->tau_mode == RLBM_TAU_CONST) {
-        if (!(p->tau > 0.0)) return RLBM_EINVAL;
+        if (!(p->tau > 0.5)) return RLBM_EINVAL;   // gamma (1 + |u|)/2 >= 1/2: unstable for every state
     } else if (p->tau_mode == RLBM_TAU_INV_THETA) {
         if (!(p->tau_a >= 0.0) || !(p->tau_b > 0.0)) return RLBM_EINVAL;
     } else {
@@ -1409,7 +1420,9 @@ void release(rlbm_ctx *c) {
 }
 
 // (Re)build the tile decomposition of every grid and, for a batch, its device tables.
+// Launches still in flight may read the tables and graphs replaced here: wait first.
 int configure(rlbm_ctx *c, int tx, int ty) {
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return RLBM_EHIP;
     drop_graphs(c);
     c->tx = tx;
     c->ty = ty;
@@ -1546,6 +1559,16 @@ int create(rlbm_ctx **out, int ngrids, const rlbm_params *p, const rlbm_init_fie
     }
     int rc = configure(c, tx, ty);
     if (!rc) rc = finish_init(c, init);
+    if (!rc) {
+        // the initial state's stability verdict (RLBM_FLAG_UNSTABLE) decides the call;
+        // other bits stay in the status word for rlbm_sync / rlbm_status
+        unsigned h = 0;
+        if (hipMemcpyAsync(&h, c->status, sizeof(unsigned), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+            hipStreamSynchronize(c->stream) != hipSuccess)
+            rc = RLBM_EHIP;
+        else if (h & RLBM_FLAG_UNSTABLE)
+            rc = RLBM_EINVAL;
+    }
     if (rc) {
         release(c);
         return rc;
@@ -1586,7 +1609,7 @@ int rlbm_step(rlbm_ctx *c, int64_t nsteps) {
         if (rc) return rc;
     }
     if (c->p[0].collect_stats) c->stat_steps += nsteps;
-    return RLBM_OK;
+    return c->p[0].check ? rlbm_sync(c) : RLBM_OK;
 }
 
 int rlbm_capture(rlbm_ctx *c) {
@@ -1663,7 +1686,12 @@ int rlbm_autotune(rlbm_ctx *c, int32_t trial_steps, int32_t *tile_x, int32_t *ti
         }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    if (c->p[0].collect_stats) c->stat_steps = -1;   // counters mixed with trial steps: invalid
+    // the trial steps counted iterations too: restart the inversion counters (the
+    // stream is idle here, and this call is never captured into a graph)
+    if (!rc && c->p[0].collect_stats) {
+        if (hipMemsetAsync(c->stats, 0, 2 * sizeof(unsigned long long), c->stream) != hipSuccess) rc = RLBM_EHIP;
+        c->stat_steps = 0;
+    }
     c->persistent = bp;
     if (!rc) rc = configure(c, bx, by);
     if (tile_x) *tile_x = bx;
@@ -1684,6 +1712,8 @@ int rlbm_moments_grid(rlbm_ctx *c, int32_t g, const rlbm_out_fields *o) {
     a.o_uy = o->uy;
     a.o_qx = o->qx;
     a.o_qy = o->qy;
+    double *const raw[9] = {o->N0, o->Nx, o->Ny, o->T00, o->T0x, o->T0y, o->Txx, o->Txy, o->Tyy};
+    for (int i = 0; i < 9; ++i) a.o_mom[i] = raw[i];
     a.stats = nullptr;
     hipLaunchKernelGGL(pick(1, c->p[0].stats, c->p[0].precision), dim3(8 * a.per_xcd), dim3(256), 0, c->stream, a);
     if (hipGetLastError() != hipSuccess) return RLBM_EHIP;
@@ -1695,7 +1725,6 @@ int rlbm_inversion_stats(rlbm_ctx *c, uint64_t *iterations, uint64_t *solves) {
     unsigned long long h[2] = {0, 0};
     if (hipMemcpyAsync(h, c->stats, sizeof(h), hipMemcpyDeviceToHost, c->stream) != hipSuccess) return RLBM_EHIP;
     if (hipStreamSynchronize(c->stream) != hipSuccess) return RLBM_EHIP;
-    if (c->stat_steps < 0) return RLBM_EINVAL;   // autotune trial steps were mixed in
     uint64_t cells = 0;
     for (const auto &a : c->base) cells += (uint64_t)a.plane;
     *iterations = h[0];
@@ -1754,7 +1783,7 @@ int rlbm_sync(rlbm_ctx *c) {
     if (h) {
         if (hipMemsetAsync(c->status, 0, sizeof(unsigned), c->stream) != hipSuccess) return RLBM_EHIP;
         if (hipStreamSynchronize(c->stream) != hipSuccess) return RLBM_EHIP;
-        return RLBM_EDOMAIN;
+        return (h & RLBM_FLAG_NONFINITE) ? RLBM_ENONFINITE : RLBM_EDOMAIN;
     }
     return RLBM_OK;
 }

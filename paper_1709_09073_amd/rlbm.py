@@ -21,8 +21,10 @@ GUESS = {"fixed": 0, "mlp": 1}
 DTYPE = {"fp64": torch.float64, "fp32": torch.float32}
 F16DEV_BYTES_PER_CELL = 180   # 72 half deviations + 9 float side values
 FIELD_NAMES = ("n", "eps", "theta", "z", "ux", "uy", "qx", "qy")
+MOMENT_NAMES = ("N0", "Nx", "Ny", "T00", "T0x", "T0y", "Txx", "Txy", "Tyy")
 
 FLAG_NONPOSITIVE, FLAG_SUPERLUMINAL, FLAG_CONDENSED, FLAG_RANGE, FLAG_NOCONV = 0x1, 0x2, 0x4, 0x8, 0x10
+FLAG_NONFINITE, FLAG_UNSTABLE = 0x20, 0x40
 MLP_HIDDEN = 32
 MLP_FLOATS = 4 + 3 * MLP_HIDDEN + 1
 MLP_NTRAIN = 3 * MLP_HIDDEN + 1
@@ -36,7 +38,7 @@ class Params(ctypes.Structure):
                 ("mlp", ctypes.c_void_p), ("f_a", ctypes.c_void_p), ("f_b", ctypes.c_void_p),
                 ("stream", ctypes.c_void_p), ("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32),
                 ("collect_stats", ctypes.c_int32), ("force", ctypes.c_double * 2), ("wall_n", ctypes.c_double),
-                ("wall_theta", ctypes.c_double)]
+                ("wall_theta", ctypes.c_double), ("check", ctypes.c_int32)]
 
 
 class InitFields(ctypes.Structure):
@@ -45,7 +47,7 @@ class InitFields(ctypes.Structure):
 
 
 class OutFields(ctypes.Structure):
-    _fields_ = [(k, ctypes.c_void_p) for k in FIELD_NAMES]
+    _fields_ = [(k, ctypes.c_void_p) for k in FIELD_NAMES + MOMENT_NAMES]
 
 
 class RlbmError(RuntimeError):
@@ -154,7 +156,8 @@ def _grid_args(params, init, device, stream):
                stream=ctypes.c_void_p(stream.cuda_stream),
                tile_x=int(params.get("tile", (0, 0))[0]), tile_y=int(params.get("tile", (0, 0))[1]),
                collect_stats=int(bool(params.get("collect_stats", False))),
-               wall_n=float(params.get("wall_n", 1.0)), wall_theta=float(params.get("wall_theta", 1.0)))
+               wall_n=float(params.get("wall_n", 1.0)), wall_theta=float(params.get("wall_theta", 1.0)),
+               check=int(bool(params.get("check", False))))
     p.bc[:] = [BC[b] for b in bc]
     p.theta_wall[:] = [float(t) for t in tw]
     p.force[:] = [float(a) for a in params.get("force", (0.0, 0.0))]
@@ -172,8 +175,8 @@ class Sim:
     bc (xlo, xhi, ylo, yhi names from BC), theta_wall (xlo, xhi), guess ('fixed'|'mlp')
     with mlp (the network's weight tensor), tile ((tile_x, tile_y), default automatic),
     collect_stats, force ((a_x, a_y), momentum update), wall_n and wall_theta (state
-    imposed on 'wall_neq' sides).  init: dict of (ny, nx) float64 CUDA tensors theta,
-    ux, uy and either n or z.
+    imposed on 'wall_neq' sides), check (every step call waits and reports the status
+    word).  init: dict of (ny, nx) float64 CUDA tensors theta, ux, uy and either n or z.
     """
 
     def __init__(self, params, init, device="cuda", stream=None):
@@ -227,8 +230,9 @@ class Sim:
         return lib().rlbm_steps_done(self.ctx)
 
     def fields(self, names=FIELD_NAMES, check=True):
+        """Fields (and, if named, raw moments MOMENT_NAMES) of the current state."""
         out = {k: torch.empty((self.ny, self.nx), dtype=torch.float64, device=self.f[0].device) for k in names}
-        of = OutFields(**{k: _ptr(out.get(k)) for k in FIELD_NAMES})
+        of = OutFields(**{k: _ptr(out.get(k)) for k in FIELD_NAMES + MOMENT_NAMES})
         rc = lib().rlbm_moments(self.ctx, ctypes.byref(of))
         if check:
             _check(rc, "rlbm_moments")
@@ -380,7 +384,7 @@ class Batch:
         p = self.params[g]
         ny, nx = int(p["ny"]), int(p["nx"])
         out = {k: torch.empty((ny, nx), dtype=torch.float64, device=self.f[g][0].device) for k in names}
-        of = OutFields(**{k: _ptr(out.get(k)) for k in FIELD_NAMES})
+        of = OutFields(**{k: _ptr(out.get(k)) for k in FIELD_NAMES + MOMENT_NAMES})
         rc = lib().rlbm_moments_grid(self.ctx, int(g), ctypes.byref(of))
         if check:
             _check(rc, "rlbm_moments_grid")

@@ -57,6 +57,7 @@ def _params(**kw):
 
 INVALID = [
     dict(nx=1), dict(ny=0), dict(stats=3), dict(order=7), dict(order=1), dict(precision=5), dict(tau=0.0),
+    dict(tau=0.5),   # gamma (1 + |u|)/2 >= 1/2 for every state: the relaxation would over-shoot
     dict(tau_mode=1, tau_b=0.0), dict(tau_mode=2), dict(bc=[0, 1, 0, 0]), dict(bc=[0, 0, 2, 2]),
     dict(bc=[2, 2, 0, 0], nx=3), dict(f_a=ctypes.c_void_p(0)), dict(f_b=ctypes.c_void_p(0x1000)),
     dict(tile_x=48, tile_y=5), dict(tile_x=8, tile_y=32), dict(tile_x=64, tile_y=2),
@@ -115,3 +116,22 @@ def test_null_context_calls(rl):
     assert L.rlbm_state_index(None) == -1
     assert L.rlbm_noneq_tensors(None, 0, None, None, None, None) == rl.RLBM_EINVAL
     L.rlbm_free(None)
+
+
+def test_struct_layouts_follow_the_header(rl):
+    """The binding's structures carry every member of the header's, in order (the
+    check flag of rlbm_params, the raw-moment outputs of rlbm_out_fields)."""
+    src = open(os.path.join(ROOT, "include", "rlbm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    for struct, cls in (("rlbm_params", rl.Params), ("rlbm_out_fields", rl.OutFields),
+                        ("rlbm_init_fields", rl.InitFields)):
+        body = re.search(r"typedef struct %s \{(.*?)\} %s;" % (struct, struct), src, flags=re.S).group(1)
+        names = []
+        for decl in body.split(";"):
+            decl = decl.strip()
+            if not decl:
+                continue
+            decl = re.sub(r"^(const\s+)?\w+\s*", "", decl)
+            for nm in decl.split(","):
+                names.append(re.sub(r"[\s*]|\[\d+\]", "", nm))
+        assert [f[0] for f in cls._fields_] == names, struct
