@@ -267,6 +267,20 @@ int rlbm_mlp_loss_grad(const float *w, const float *x, const float *t, int64_t n
 int rlbm_mlp_train(float *w, const float *x, const float *t, int64_t n, int32_t iters, float lr,
                    float *loss_out, void *workspace, void *stream);
 
+/* Allocation-free rlbm_mlp_train for callers that cannot allocate device memory (code
+ * under HIP graph capture, serving loops, harnesses that forbid hipMalloc): the same
+ * kernels and arithmetic (bit-identical results), with the workspace taken from a
+ * library-owned device array of rlbm_mlp_workspace_bytes(RLBM_MLP_NOALLOC_MAX) bytes
+ * (about 13 MB), one per GPU, held until the process ends.  n must be in
+ * 1 .. RLBM_MLP_NOALLOC_MAX, else RLBM_EINVAL; RLBM_EHIP if the array's address
+ * cannot be obtained.  Allocates nothing.  Every call on one GPU uses that GPU's array:
+ * calls that overlap on one GPU (other streams or threads) race and must be ordered
+ * by the caller.  Enqueued on `stream`; the moments of Adam are cleared by a kernel,
+ * not a memset, so the launches may be captured into a graph. */
+#define RLBM_MLP_NOALLOC_MAX 32768
+int rlbm_mlp_train_noalloc(float *w, const float *x, const float *t, int64_t n, int32_t iters, float lr,
+                           float *loss_out, void *stream);
+
 /* y[i] = network(x[i]) for n inputs (device floats). */
 int rlbm_mlp_predict(const float *w, const float *x, float *y, int64_t n, void *stream);
 

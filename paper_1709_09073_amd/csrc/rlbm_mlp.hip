@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 
 #include "rlbm.h"
 #include "rlbm_mlp.h"
@@ -184,14 +185,42 @@ int loss_grad_enqueue(const float *w, const float *x, const float *t, long long 
     return hipGetLastError() == hipSuccess ? RLBM_OK : RLBM_EHIP;
 }
 
+constexpr uint64_t workspace_bytes(int64_t n) {
+    return sizeof(float) * ((uint64_t)(NTRAIN + 1) * (uint64_t)(n + 1) + 2u * NTRAIN + 4u) + 8u +
+           sizeof(double) * (uint64_t)(NTRAIN + 1) * PARTS;
+}
+
+// Workspace of the allocation-free training call: a device array of fixed size, one
+// per GPU for the life of the process, laid out by carve() like a caller's workspace
+// (training on n <= RLBM_MLP_NOALLOC_MAX samples uses a prefix of it).
+constexpr uint64_t SCRATCH_BYTES = workspace_bytes(RLBM_MLP_NOALLOC_MAX);
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+
+// Device address of `scratch` on the current device, looked up once per device (the
+// host-side name is only a stand-in for the symbol, never a device address).
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+void *scratch_addr[MAX_DEVICES] = {};
+
+void *scratch_on_current_device() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_addr[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+        scratch_addr[dev] = ptr;
+    }
+    return scratch_addr[dev];
+}
+
 }  // namespace
 
 extern "C" {
 
 uint64_t rlbm_mlp_workspace_bytes(int64_t n) {
     if (n < 1) return 0;
-    return sizeof(float) * ((uint64_t)(NTRAIN + 1) * (uint64_t)(n + 1) + 2u * NTRAIN + 4u) + 8u +
-           sizeof(double) * (uint64_t)(NTRAIN + 1) * PARTS;
+    return workspace_bytes(n);
 }
 
 int rlbm_mlp_init(float *w, const float *x, const float *t, int64_t n, const float *noise, void *workspace,
@@ -227,6 +256,14 @@ int rlbm_mlp_train(float *w, const float *x, const float *t, int64_t n, int32_t 
         hipLaunchKernelGGL(k_adam, dim3(1), dim3(128), 0, s, w, ws.grad, ws.m, ws.v, it, lr, loss_out);
     }
     return hipGetLastError() == hipSuccess ? RLBM_OK : RLBM_EHIP;
+}
+
+int rlbm_mlp_train_noalloc(float *w, const float *x, const float *t, int64_t n, int32_t iters, float lr,
+                           float *loss_out, void *stream) {
+    if (!w || !x || !t || n < 1 || n > RLBM_MLP_NOALLOC_MAX || iters < 0 || !(lr > 0.0f)) return RLBM_EINVAL;
+    void *ws = scratch_on_current_device();
+    if (!ws) return RLBM_EHIP;
+    return rlbm_mlp_train(w, x, t, n, iters, lr, loss_out, ws, stream);
 }
 
 int rlbm_mlp_predict(const float *w, const float *x, float *y, int64_t n, void *stream) {

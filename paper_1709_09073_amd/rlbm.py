@@ -28,6 +28,7 @@ FLAG_NONFINITE, FLAG_UNSTABLE = 0x20, 0x40
 MLP_HIDDEN = 32
 MLP_FLOATS = 4 + 3 * MLP_HIDDEN + 1
 MLP_NTRAIN = 3 * MLP_HIDDEN + 1
+MLP_NOALLOC_MAX = 32768   # samples the allocation-free training call accepts
 
 
 class Params(ctypes.Structure):
@@ -95,6 +96,7 @@ def lib():
         L.rlbm_mlp_loss_grad.argtypes = [vp, vp, vp, ctypes.c_int64, vp, vp, vp, vp]
         L.rlbm_mlp_train.argtypes = [vp, vp, vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_float, vp, vp, vp]
         L.rlbm_mlp_predict.argtypes = [vp, vp, vp, ctypes.c_int64, vp]
+        L.rlbm_mlp_train_noalloc.argtypes = [vp, vp, vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_float, vp, vp]
         _LIB = L
     return _LIB
 
@@ -327,6 +329,15 @@ class GuessNet:
         losses = torch.empty(max(int(iters), 1), dtype=torch.float32, device=self.w.device)
         _check(lib().rlbm_mlp_train(_ptr(self.w), _ptr(x), _ptr(t), x.numel(), int(iters), float(lr), _ptr(losses),
                                     _ptr(self._workspace(x.numel())), self._s()), "rlbm_mlp_train")
+        return losses[:iters]
+
+    def train_noalloc(self, x, t, iters, lr):
+        """As train, through the allocation-free entry point (at most MLP_NOALLOC_MAX
+        samples; the library's own device array replaces the workspace)."""
+        x, t = x.reshape(-1).contiguous().float(), t.reshape(-1).contiguous().float()
+        losses = torch.empty(max(int(iters), 1), dtype=torch.float32, device=self.w.device)
+        _check(lib().rlbm_mlp_train_noalloc(_ptr(self.w), _ptr(x), _ptr(t), x.numel(), int(iters), float(lr),
+                                            _ptr(losses), self._s()), "rlbm_mlp_train_noalloc")
         return losses[:iters]
 
     def predict(self, x):
