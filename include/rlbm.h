@@ -19,7 +19,7 @@
  *    cells; inside block n the six shells of a cell form 16-byte records: FP32
  *    (float) shells 0..3 at byte 16*c, shells 4..5 at 16*P + 8*c; FP64 (double)
  *    shells 2j, 2j+1 at 16*j*P + 16*c (j = 0, 1, 2).  72*nx*ny elements per buffer.
- *    RLBM_F16DEV buffers hold 180*nx*ny bytes (layout at enum rlbm_precision).
+ *    RLBM_DEV16 buffers hold 192*nx*ny bytes (layout at enum rlbm_precision).
  *  - The stored state is the post-collision population.  One step is: pull
  *    streaming, moments N^mu and T^{mu nu}, Landau frame (Eq. eigen-eq), density
  *    (Eq. density-eq), inversion to (theta, z), relaxation time, fifth-order
@@ -63,14 +63,15 @@ enum rlbm_status_code {
 };
 
 enum rlbm_stats { RLBM_MJ = 0, RLBM_FD = 1, RLBM_BE = 2 };         /* Eqs. mj-w-eq, fd-w-eq, be-w-eq */
-/* Population storage.  RLBM_F16DEV (project extension): per cell the deviations
- * e_i = (f_i / w_k - R_i) / s as IEEE half, R_{k,n} = rho_k + p_k (alpha cos phi_n
- * + beta sin phi_n) (direction average of f/w per shell plus a least-squares
- * p-weighted dipole), s = max_i |f_i / w_k - R_i|.  A buffer holds 12 direction
- * blocks, each nx*ny cells (y-major, x fastest) of 6 halves (shells k = 0..5, 12
- * bytes), then nx*ny cells of 9 floats rho_0..rho_5, alpha, beta, s (36 bytes): 180
- * bytes per cell.  Arithmetic as RLBM_FP32. */
-enum rlbm_precision { RLBM_FP64 = 0, RLBM_FP32 = 1, RLBM_F16DEV = 2 };
+/* Population storage.  RLBM_DEV16 (project extension): per cell the deviations
+ * e_i = (f_i / w_k - R_i) / s_k as SNORM16 (q = round(32767 e), |e| <= 1), with
+ * R_{k,n} = rho_k + p_k (alpha cos phi_n + beta sin phi_n) (direction average of f/w per
+ * shell plus a least-squares p-weighted dipole) and one scale per shell,
+ * s_k >= max_n |f_{k,n} / w_k - R_{k,n}| (an IEEE half, rounded up).  A buffer holds 12
+ * direction blocks, each nx*ny cells (y-major, x fastest) of 6 SNORM16 (shells k = 0..5,
+ * 12 bytes), then nx*ny cells of 48 bytes: floats rho_0..rho_5, alpha, beta, halves
+ * s_0..s_5, 4 bytes of padding: 192 bytes per cell.  Arithmetic as RLBM_FP32. */
+enum rlbm_precision { RLBM_FP64 = 0, RLBM_FP32 = 1, RLBM_DEV16 = 2 };
 enum rlbm_tau_mode { RLBM_TAU_CONST = 0, RLBM_TAU_INV_THETA = 1 };  /* tau, or tau_a/theta + tau_b */
 enum rlbm_bc {
     RLBM_BC_PERIODIC = 0, /* wrap (both sides of an axis must be periodic) */
@@ -106,7 +107,7 @@ typedef struct rlbm_params {
     int32_t guess;           /* rlbm_guess */
     const float *mlp;        /* device pointer to the MLP weights (RLBM_GUESS_MLP), else NULL */
     void *f_a, *f_b;         /* device population buffers (ping-pong), 72*nx*ny elements each
-                                (F16DEV: 180*nx*ny bytes each, 4-byte aligned) */
+                                (DEV16: 192*nx*ny bytes each, 16-byte aligned) */
     void *stream;            /* hipStream_t, NULL = default stream */
     int32_t tile_x, tile_y;  /* cells per workgroup tile, tile_x * tile_y = 256 with tile_x a power
                                 of two >= 16; 0, 0 = automatic (32 x 8; 128 x 2 when nx >= 4096;

@@ -288,7 +288,7 @@ struct Mom {
     double N0, Nx, Ny, T00, T01, T02, T11, T12, T22;
 };
 
-// GU: f holds f_i / w_k (the FP16-deviation path works in those units); the
+// GU: f holds f_i / w_k (the 16-bit deviation path works in those units); the
 // weights fold into the constants.
 template <int ST, typename R, bool GU = false>
 __device__ __forceinline__ Mom moments(const R (&f)[72]) {
@@ -392,7 +392,7 @@ __device__ __forceinline__ void g_table(const double (*tab)[NG], int i, double d
     }
 }
 
-// LOOSE (FP32 / FP16 populations): shortened sums, tail below 1e-11 relative
+// LOOSE (FP32 / 16-bit populations): shortened sums, tail below 1e-11 relative
 // (bounded when the tables are generated).
 template <int ST, int MLO, int MHI, bool LOOSE = false>
 __device__ __forceinline__ void gvals(double mu, double (&g)[7], unsigned &flags) {
@@ -459,7 +459,7 @@ __device__ __forceinline__ double rcp_refined(double x) {
 // Newton on mu = ln z leaves an error C dmu^2 after a step dmu, with C = f''/(2 f')
 // at most 0.5 for FD and about 0.5/|mu| for BE near mu = 0, so a step below this
 // tolerance is applied and ends the solve (no confirming evaluation).  FP64
-// populations: 1e-8 (error <= 5e-17); FP32/FP16 populations: 1e-5 (error <= 5e-11,
+// populations: 1e-8 (error <= 5e-17); FP32/16-bit populations: 1e-5 (error <= 5e-11,
 // far below the populations' own rounding).
 template <int ST, bool LOOSE>
 __device__ __forceinline__ double newton_tol(double mu) {
@@ -749,130 +749,294 @@ __device__ __forceinline__ void store(S *__restrict__ fout, long long plane, int
     }
 }
 
-// ---------------------------------------------------------------- FP16 deviation storage
-// Per cell: e_i = (f_i / w_k - R_i) / s stored as IEEE half, with the reference
+// ---------------------------------------------------------------- 16-bit deviation storage
+// Per cell: e_i = (f_i / w_k - R_i) / s_k stored as a signed normalized 16-bit integer
+// (SNORM16: q = round(32767 e), |e| <= 1), with the reference
 // R_{k,n} = rho_k + p_k (alpha cos phi_n + beta sin phi_n) (the direction average of
-// f/w per shell plus one p-weighted dipole, least squares) and the scale
-// s = max_i |f_i / w_k - R_i|.  Buffer layout (180 bytes per cell): 12 direction
-// blocks of nx*ny cells x 6 halves (12 bytes per cell, shells k = 0..5 in order),
-// then nx*ny cells x 9 floats rho_0..rho_5, alpha, beta, s (36 bytes per cell).  A
-// direction's six deviations of a cell are one 12-byte load; a cell's side values
-// three.  The reference is linear in the side values, so a pull interpolates the side
-// values with the bilinear weights and the deviations with the weights times the
-// source scales.
+// f/w per shell plus one p-weighted dipole, least squares) and a scale per shell,
+// s_k >= max_n |f_{k,n} / w_k - R_{k,n}|, kept as IEEE half (rounded up).  Fixed point
+// gives every value of a shell the same absolute step s_k / 32767, and the per-shell
+// scale keeps the inner shells, which carry the density, energy and momentum, at
+// their own small residuals.  Buffer layout (192 bytes per cell): 12 direction blocks
+// of nx*ny cells x 6 SNORM16 (12 bytes per cell, shells k = 0..5 in order), then nx*ny
+// cells x 48 bytes: floats rho_0..rho_5, alpha, beta, then halves s_0..s_5, then 4
+// bytes of padding.  A direction's six deviations of a cell are one 12-byte load; a
+// cell's side record three 16-byte loads.  The reference is linear in the side values,
+// so a pull interpolates the side values with the bilinear weights and the
+// deviations with the weights times the source's shell scales.
 struct Dev16 {};
 
-// half k (0..5) of a cell's packed deviations
-__device__ __forceinline__ float dev_half(const u32x3 &v, int k) {
+constexpr float SNORM16_STEP = 1.0f / 32767.0f;
+
+// deviation k (0..5) of a cell's packed record, as the integer value in float
+__device__ __forceinline__ float dev_value(const u32x3 &v, int k) {
     const unsigned u = v[k >> 1];
-    const f16x2 h = __builtin_bit_cast(f16x2, u);
-    return (float)((k & 1) ? h.y : h.x);
+    return (k & 1) ? (float)((int)u >> 16) : (float)(short)(u & 0xffffu);
 }
 
+__device__ __forceinline__ float half_lo(unsigned u) { return (float)__builtin_bit_cast(f16x2, u).x; }
+__device__ __forceinline__ float half_hi(unsigned u) { return (float)__builtin_bit_cast(f16x2, u).y; }
+
 struct SideRef {
-    float v[8];   // rho_0..rho_5, alpha, beta
-    float s;      // scale
+    float v[8];        // rho_0..rho_5, alpha, beta
+    unsigned s[3];     // shell scales as half pairs (s_0, s_1), (s_2, s_3), (s_4, s_5)
+    __device__ __forceinline__ float scale(int k) const { return (k & 1) ? half_hi(s[k >> 1]) : half_lo(s[k >> 1]); }
 };
 
 __device__ __forceinline__ void load_side(rsrc_t rs, unsigned cell, SideRef &o) {
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        const u32x3 w = __builtin_amdgcn_raw_buffer_load_b96(rs, cell * 36u, (unsigned)j * 12u, LOAD_POLICY);
-        const float a = u32_as_float(w[0]), b = u32_as_float(w[1]), c = u32_as_float(w[2]);
-        o.v[3 * j] = a;
-        o.v[3 * j + 1] = b;
-        if (j < 2) o.v[3 * j + 2] = c;
-        else o.s = c;
-    }
+    const u32x4 a = __builtin_amdgcn_raw_buffer_load_b128(rs, cell * 48u, 0u, LOAD_POLICY);
+    const u32x4 b = __builtin_amdgcn_raw_buffer_load_b128(rs, cell * 48u, 16u, LOAD_POLICY);
+    const u32x4 c = __builtin_amdgcn_raw_buffer_load_b128(rs, cell * 48u, 32u, LOAD_POLICY);
+    unsigned a0 = a[0], a1 = a[1], a2 = a[2], a3 = a[3], b0 = b[0], b1 = b[1], b2 = b[2], b3 = b[3];
+    o.v[0] = u32_as_float(a0);
+    o.v[1] = u32_as_float(a1);
+    o.v[2] = u32_as_float(a2);
+    o.v[3] = u32_as_float(a3);
+    o.v[4] = u32_as_float(b0);
+    o.v[5] = u32_as_float(b1);
+    o.v[6] = u32_as_float(b2);
+    o.v[7] = u32_as_float(b3);
+    o.s[0] = c[0];
+    o.s[1] = c[1];
+    o.s[2] = c[2];
 }
 
-// One direction n: taps (cell index, weight times the source's scale) and the side
-// values already interpolated to the departure point (rho_0..rho_5, alpha, beta).
-template <int ST, int N, int NT>
-__device__ __forceinline__ void dev_direction(const char *base, long long plane, const unsigned (&cell)[NT],
-                                              const float (&ws)[NT], const float (&iv)[8], float (&f)[72]) {
-    const rsrc_t r = make_rsrc(base + (long long)N * plane * 12, 12u * (unsigned)plane);
-    u32x3 d[NT];
+// The populations of direction N of one source cell, decoded to f/w: the reference
+// rho_k + p_k (alpha cos phi_N + beta sin phi_N) plus the deviation times the shell's
+// step s_k / 32767.  Every pull decodes a source value this way, so the tile-staged
+// pull and the direct one give the same bits.
+// A source cell's side record ready for decoding: rho_0..rho_5, alpha, beta and the
+// code steps s_k / 32767.
+struct DecodeRef {
+    float v[8];
+    float step[6];
+};
+
+__device__ __forceinline__ DecodeRef decode_ref(const SideRef &sr) {
+    DecodeRef d;
 #pragma unroll
-    for (int t = 0; t < NT; ++t) d[t] = __builtin_amdgcn_raw_buffer_load_b96(r, cell[t] * 12u, 0u, LOAD_POLICY);
-    const float tn = fma_c(iv[7], sdir(N), fma_c(iv[6], cdir(N), -0.0f));
+    for (int k = 0; k < 8; ++k) d.v[k] = sr.v[k];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) d.step[k] = sr.scale(k) * SNORM16_STEP;
+    return d;
+}
+
+template <int ST, int N>
+__device__ __forceinline__ void dev_decode(const DecodeRef &d, const u32x3 &q, float (&g)[6]) {
+    const float tn = fma_c(d.v[7], sdir(N), fma_c(d.v[6], cdir(N), -0.0f));
+#pragma unroll
+    for (int k = 0; k < 6; ++k) g[k] = fmaf(d.step[k], dev_value(q, k), fmaf((float)P_SHELL[ST][k], tn, d.v[k]));
+}
+
+// Bilinear interpolation of direction N's six shells from the decoded sources at
+// (xb, yb), (x, yb), (xb, y), (x, y): the same weights and order as the FP32 pull.
+template <int N>
+__device__ __forceinline__ void dev_interp(const float (&bb)[6], const float (&bx)[6], const float (&cb)[6],
+                                           const float (&cx)[6], float (&f)[72]) {
+    const float wA = (float)(S3H * 0.5), wB = (float)((1.0 - S3H) * 0.5);
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-        float acc = iv[k] + (float)P_SHELL[ST][k] * tn;
-#pragma unroll
-        for (int t = 0; t < NT; ++t) acc += ws[t] * dev_half(d[t], k);
-        f[6 * N + k] = acc;   // f_i / w_k
+        if (N == 1 || N == 5 || N == 7 || N == 11)   // |v_x| = sqrt3/2, |v_y| = 1/2
+            f[6 * N + k] = wA * (bb[k] + cb[k]) + wB * (bx[k] + cx[k]);
+        else                                          // |v_x| = 1/2, |v_y| = sqrt3/2
+            f[6 * N + k] = wA * (bb[k] + bx[k]) + wB * (cb[k] + cx[k]);
     }
 }
 
-// The two off-axis directions of a quadrant pull from the same four cells: D (the
-// diagonal neighbour), A and B (the neighbours along x and y) and C (the cell).  One
-// weights (D, A, B, C) by (wA, wA, wB, wB), the other by (wA, wB, wA, wB); the part
-// wA D + wB C is shared.
-__device__ __forceinline__ void quad_interp(const SideRef &D, const SideRef &A, const SideRef &B, const SideRef &C,
-                                            float wA, float wB, float (&ia)[8], float (&ib)[8]) {
+template <int ST, int N>
+__device__ __forceinline__ void dev_tap(const char *base, rsrc_t rs, long long plane, unsigned cell, float (&g)[6]) {
+    const rsrc_t r = make_rsrc(base + (long long)N * plane * 12, 12u * (unsigned)plane);
+    SideRef sr;
+    load_side(rs, cell, sr);
+    const u32x3 q = __builtin_amdgcn_raw_buffer_load_b96(r, cell * 12u, 0u, LOAD_POLICY);
+    dev_decode<ST, N>(decode_ref(sr), q, g);
+}
+
+template <int ST, int N>
+__device__ __forceinline__ void dev_pull_direction(const char *base, rsrc_t rs, long long plane, int nx, int x, int y,
+                                                   int xl, int xr, int yd, int yu, float (&f)[72]) {
+    const unsigned oc = (unsigned)(y * nx), od = (unsigned)(yd * nx), ou = (unsigned)(yu * nx);
+    const unsigned xb = cdir(N) > 0.1 ? xl : xr;
+    const unsigned rb = sdir(N) > 0.1 ? od : ou;
+    if constexpr (N % 3 == 0) {
+        const unsigned src = N == 0 ? oc + xl : N == 3 ? od + x : N == 6 ? oc + xr : ou + x;
+        float g[6];
+        dev_tap<ST, N>(base, rs, plane, src, g);
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        const float k = wA * D.v[j] + wB * C.v[j];
-        ia[j] = k + wA * A.v[j] + wB * B.v[j];
-        ib[j] = k + wB * A.v[j] + wA * B.v[j];
+        for (int k = 0; k < 6; ++k) f[6 * N + k] = g[k];
+    } else {
+        float bb[6], bx[6], cb[6], cx[6];
+        dev_tap<ST, N>(base, rs, plane, rb + xb, bb);
+        dev_tap<ST, N>(base, rs, plane, rb + x, bx);
+        dev_tap<ST, N>(base, rs, plane, oc + xb, cb);
+        dev_tap<ST, N>(base, rs, plane, oc + x, cx);
+        dev_interp<N>(bb, bx, cb, cx, f);
     }
 }
 
+// Direct pull of a cell (no staging): every tap decoded from global memory.
 template <int ST>
 __device__ __forceinline__ void pull_dev(const void *fin, long long plane, int nx, int x, int y, int xl, int xr, int yd,
                                          int yu, float (&f)[72]) {
     const char *base = (const char *)fin;
-    const rsrc_t rs = make_rsrc(base + 144LL * plane, 36u * (unsigned)plane);
-    const unsigned cc = y * nx + x, cl = y * nx + xl, cr = y * nx + xr;
-    const unsigned dc = yd * nx + x, dl = yd * nx + xl, dr = yd * nx + xr;
-    const unsigned uc = yu * nx + x, ul = yu * nx + xl, ur = yu * nx + xr;
-    const float wA = (float)(S3H * 0.5), wB = (float)((1.0 - S3H) * 0.5);
-    SideRef C, A, B, D;
-    float ia[8], ib[8];
-    load_side(rs, cc, C);
-    const float sC = C.s;
-    // quadrant towards -x, -y: A = left, B = down; axis directions 0 and 3
-    load_side(rs, cl, A);
-    load_side(rs, dc, B);
-    load_side(rs, dl, D);
-    dev_direction<ST, 0, 1>(base, plane, {cl}, {A.s}, A.v, f);
-    dev_direction<ST, 3, 1>(base, plane, {dc}, {B.s}, B.v, f);
-    quad_interp(D, A, B, C, wA, wB, ia, ib);
-    dev_direction<ST, 1, 4>(base, plane, {dl, cl, dc, cc}, {wA * D.s, wA * A.s, wB * B.s, wB * sC}, ia, f);
-    dev_direction<ST, 2, 4>(base, plane, {dl, dc, cl, cc}, {wA * D.s, wA * B.s, wB * A.s, wB * sC}, ib, f);
-    // quadrant towards +x, -y: A = right, B = down (kept); axis direction 6
-    load_side(rs, cr, A);
-    load_side(rs, dr, D);
-    dev_direction<ST, 6, 1>(base, plane, {cr}, {A.s}, A.v, f);
-    quad_interp(D, A, B, C, wA, wB, ia, ib);
-    dev_direction<ST, 4, 4>(base, plane, {dr, dc, cr, cc}, {wA * D.s, wA * B.s, wB * A.s, wB * sC}, ib, f);
-    dev_direction<ST, 5, 4>(base, plane, {dr, cr, dc, cc}, {wA * D.s, wA * A.s, wB * B.s, wB * sC}, ia, f);
-    // quadrant towards +x, +y: A = right (kept), B = up; axis direction 9
-    load_side(rs, uc, B);
-    load_side(rs, ur, D);
-    dev_direction<ST, 9, 1>(base, plane, {uc}, {B.s}, B.v, f);
-    quad_interp(D, A, B, C, wA, wB, ia, ib);
-    dev_direction<ST, 7, 4>(base, plane, {ur, cr, uc, cc}, {wA * D.s, wA * A.s, wB * B.s, wB * sC}, ia, f);
-    dev_direction<ST, 8, 4>(base, plane, {ur, uc, cr, cc}, {wA * D.s, wA * B.s, wB * A.s, wB * sC}, ib, f);
-    // quadrant towards -x, +y: A = left, B = up (kept)
-    load_side(rs, cl, A);
-    load_side(rs, ul, D);
-    quad_interp(D, A, B, C, wA, wB, ia, ib);
-    dev_direction<ST, 10, 4>(base, plane, {ul, uc, cl, cc}, {wA * D.s, wA * B.s, wB * A.s, wB * sC}, ib, f);
-    dev_direction<ST, 11, 4>(base, plane, {ul, cl, uc, cc}, {wA * D.s, wA * A.s, wB * B.s, wB * sC}, ia, f);
+    const rsrc_t rs = make_rsrc(base + 144LL * plane, 48u * (unsigned)plane);
+    dev_pull_direction<ST, 0>(base, rs, plane, nx, x, y, xl, xr, yd, yu, f);
+    dev_pull_direction<ST, 1>(base, rs, plane, nx, x, y, xl, xr, yd, yu, f);
+    dev_pull_direction<ST, 2>(base, rs, plane, nx, x, y, xl, xr, yd, yu, f);
+    dev_pull_direction<ST, 3>(base, rs, plane, nx, x, y, xl, xr, yd, yu, f);
+    dev_pull_direction<ST, 4>(base, rs, plane, nx, x, y, xl, xr, yd, yu, f);
+    dev_pull_direction<ST, 5>(base, rs, plane, nx, x, y, xl, xr, yd, yu, f);
+    dev_pull_direction<ST, 6>(base, rs, plane, nx, x, y, xl, xr, yd, yu, f);
+    dev_pull_direction<ST, 7>(base, rs, plane, nx, x, y, xl, xr, yd, yu, f);
+    dev_pull_direction<ST, 8>(base, rs, plane, nx, x, y, xl, xr, yd, yu, f);
+    dev_pull_direction<ST, 9>(base, rs, plane, nx, x, y, xl, xr, yd, yu, f);
+    dev_pull_direction<ST, 10>(base, rs, plane, nx, x, y, xl, xr, yd, yu, f);
+    dev_pull_direction<ST, 11>(base, rs, plane, nx, x, y, xl, xr, yd, yu, f);
 }
 
-// (a c, b c) rounded once each to IEEE half and packed low, high: v_fma_mix takes the
-// FP32 operands and rounds the exact product (one instruction per value instead of
-// a multiply per value and a conversion per pair).  mixlo leaves the high half of
-// its destination alone; mixhi then writes it.
-__device__ __forceinline__ unsigned scaled_f16x2(float a, float b, float c) {
-    unsigned r;
-    asm("v_fma_mixlo_f16 %0, %1, %2, 0" : "=v"(r) : "v"(a), "v"(c));
-    asm("v_fma_mixhi_f16 %0, %1, %2, 0" : "+v"(r) : "v"(b), "v"(c));
-    return r;
+// ---------------------------------------------------------------- tile-staged pull (16-bit deviations)
+// A workgroup covers a tile of tx x ty cells; its halo tile of (tx + 2) x (ty + 2) source
+// cells is decoded once per direction into LDS (six floats per cell, f/w), and every
+// cell then interpolates its direction from LDS.  Each source value is decoded about
+// 1.3 times per step (the halo) instead of up to four times (once per pulling cell).
+// Two LDS buffers alternate between directions, so one barrier per direction suffices.
+// Halo cell h (row-major in the halo tile) is decoded by thread h and, for h >= 256,
+// by thread h - 256; tiles with more than 512 halo cells use the direct pull.
+constexpr int DEV16_MAX_HALO = 512;
+
+// source coordinate of a halo position (one step outside the grid at most matters;
+// positions further out feed only cells outside the grid and are clamped in bounds)
+__device__ __forceinline__ int halo_src(int g, int n, int bc_lo, int bc_hi) {
+    if (g < 0) return bc_lo == RLBM_BC_PERIODIC ? n - 1 : 0;
+    if (g >= n) return (bc_hi == RLBM_BC_PERIODIC && g == n) ? 0 : n - 1;
+    return g;
 }
+
+struct HaloCell {
+    DecodeRef d;
+    unsigned cell;
+    bool valid;
+};
+
+template <int N>
+__device__ __forceinline__ void dev_load_halo(const char *base, long long plane, const HaloCell (&hc)[2],
+                                              u32x3 (&q)[2]) {
+    const rsrc_t r = make_rsrc(base + (long long)N * plane * 12, 12u * (unsigned)plane);
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+        q[j] = hc[j].valid ? __builtin_amdgcn_raw_buffer_load_b96(r, hc[j].cell * 12u, 0u, LOAD_POLICY) : u32x3{0u, 0u, 0u};
+}
+
+template <int ST, int N>
+__device__ __forceinline__ void dev_stage_direction(const HaloCell (&hc)[2], const u32x3 (&q)[2], int tid, float *buf) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        if (!hc[j].valid) continue;
+        float g[6];
+        dev_decode<ST, N>(hc[j].d, q[j], g);
+        float *dst = buf + 6 * (tid + 256 * j);
+#pragma unroll
+        for (int k = 0; k < 6; k += 2) *reinterpret_cast<float2 *>(dst + k) = make_float2(g[k], g[k + 1]);
+    }
+}
+
+template <int N>
+__device__ __forceinline__ void dev_read_tap(const float *buf, int h, float (&g)[6]) {
+    const float *src = buf + 6 * h;
+#pragma unroll
+    for (int k = 0; k < 6; k += 2) {
+        const float2 v = *reinterpret_cast<const float2 *>(src + k);
+        g[k] = v.x;
+        g[k + 1] = v.y;
+    }
+}
+
+// Direction N of the cell at halo position (hx, hy) from the staged buffer.
+template <int N>
+__device__ __forceinline__ void dev_lds_direction(const float *buf, int hw, int hx, int hy, float (&f)[72]) {
+    const int xb = cdir(N) > 0.1 ? hx - 1 : (cdir(N) < -0.1 ? hx + 1 : hx);
+    const int yb = sdir(N) > 0.1 ? hy - 1 : (sdir(N) < -0.1 ? hy + 1 : hy);
+    if constexpr (N % 3 == 0) {
+        float g[6];
+        dev_read_tap<N>(buf, yb * hw + xb, g);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) f[6 * N + k] = g[k];
+    } else {
+        float bb[6], bx[6], cb[6], cx[6];
+        dev_read_tap<N>(buf, yb * hw + xb, bb);
+        dev_read_tap<N>(buf, yb * hw + hx, bx);
+        dev_read_tap<N>(buf, hy * hw + xb, cb);
+        dev_read_tap<N>(buf, hy * hw + hx, cx);
+        dev_interp<N>(bb, bx, cb, cx, f);
+    }
+}
+
+// One direction of the staged pull.  The halo's packed deviations of direction N
+// arrived in q during the previous round; direction N + 1's are requested first, so
+// their latency overlaps this round's decode, barrier and interpolation.
+template <int ST, int N>
+__device__ __forceinline__ void dev_tile_round(const char *base, long long plane, const HaloCell (&hc)[2], int tid,
+                                               float *lds, int nh, int hw, int hx, int hy, bool use, u32x3 (&q)[2],
+                                               float (&f)[72]) {
+    u32x3 qn[2];
+    if constexpr (N < 11) dev_load_halo<N + 1>(base, plane, hc, qn);
+    float *buf = lds + (N & 1) * 6 * nh;
+    dev_stage_direction<ST, N>(hc, q, tid, buf);
+    __syncthreads();
+    if (use) dev_lds_direction<N>(buf, hw, hx, hy, f);
+    if constexpr (N < 11) {
+        q[0] = qn[0];
+        q[1] = qn[1];
+    }
+}
+
+// Tile-staged pull for the workgroup's tile at (x0, y0) of grid a.  Every thread of the
+// workgroup calls it (it holds barriers); `use` says whether this thread's own pull
+// position (hx, hy) (halo coordinates, its stencil inside the halo tile) takes the
+// staged values.
+template <int ST>
+__device__ __forceinline__ void dev_tile_pull(const KArgs &a, int x0, int y0, float *lds, int hx, int hy, bool use,
+                                              float (&f)[72]) {
+    const char *base = (const char *)a.fin;
+    const int tid = (int)threadIdx.x;
+    const int hw = a.tx + 2, nh = hw * (a.ty + 2);
+    const rsrc_t rs = make_rsrc(base + 144LL * a.plane, 48u * (unsigned)a.plane);
+    HaloCell hc[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int h = tid + 256 * j;
+        hc[j].valid = h < nh;
+        const int hxx = h % hw, hyy = h / hw;
+        const int sx = halo_src(x0 - 1 + hxx, a.nx, a.bc_xlo, a.bc_xhi);
+        const int sy = halo_src(y0 - 1 + hyy, a.ny, a.bc_ylo, a.bc_yhi);
+        hc[j].cell = hc[j].valid ? (unsigned)(sy * a.nx + sx) : 0u;
+        if (hc[j].valid) {
+            SideRef sr;
+            load_side(rs, hc[j].cell, sr);
+            hc[j].d = decode_ref(sr);
+        }
+    }
+    u32x3 q[2];
+    dev_load_halo<0>(base, a.plane, hc, q);
+    dev_tile_round<ST, 0>(base, a.plane, hc, tid, lds, nh, hw, hx, hy, use, q, f);
+    dev_tile_round<ST, 1>(base, a.plane, hc, tid, lds, nh, hw, hx, hy, use, q, f);
+    dev_tile_round<ST, 2>(base, a.plane, hc, tid, lds, nh, hw, hx, hy, use, q, f);
+    dev_tile_round<ST, 3>(base, a.plane, hc, tid, lds, nh, hw, hx, hy, use, q, f);
+    dev_tile_round<ST, 4>(base, a.plane, hc, tid, lds, nh, hw, hx, hy, use, q, f);
+    dev_tile_round<ST, 5>(base, a.plane, hc, tid, lds, nh, hw, hx, hy, use, q, f);
+    dev_tile_round<ST, 6>(base, a.plane, hc, tid, lds, nh, hw, hx, hy, use, q, f);
+    dev_tile_round<ST, 7>(base, a.plane, hc, tid, lds, nh, hw, hx, hy, use, q, f);
+    dev_tile_round<ST, 8>(base, a.plane, hc, tid, lds, nh, hw, hx, hy, use, q, f);
+    dev_tile_round<ST, 9>(base, a.plane, hc, tid, lds, nh, hw, hx, hy, use, q, f);
+    dev_tile_round<ST, 10>(base, a.plane, hc, tid, lds, nh, hw, hx, hy, use, q, f);
+    dev_tile_round<ST, 11>(base, a.plane, hc, tid, lds, nh, hw, hx, hy, use, q, f);
+}
+
+// Shell scale kept as an IEEE half no smaller than s: s (1 + 2^-10) + 2^-24 rounds to
+// nearest at most 2^-11 s (normal halves) or 2^-25 (subnormals) below itself.
+__device__ __forceinline__ _Float16 scale_half(float s) { return (_Float16)fmaf(s, 1.0009765625f, 5.9604645e-8f); }
+
+typedef short s16x2 __attribute__((ext_vector_type(2)));
 
 template <int ST>
 __device__ __forceinline__ void store_dev(void *fout, long long plane, int off, const float (&f)[72]) {
@@ -904,19 +1068,25 @@ __device__ __forceinline__ void store_dev(void *fout, long long plane, int off, 
     // least-squares dipole: sum_n cos^2 = 6 over the 12 directions
     const float inv_den = (float)(1.0 / (6.0 * pp));
     const float alpha = A * inv_den, beta = B * inv_den;
-    float smax = 0.0f;
+    float smax[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int n = 0; n < 12; ++n) {
         const float tn = fma_c(beta, sdir(n), fma_c(alpha, cdir(n), -0.0f));
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
             g[6 * n + k] -= rho[k] + (float)P_SHELL[ST][k] * tn;
-            smax = fmaxf(smax, fabsf(g[6 * n + k]));
+            smax[k] = fmaxf(smax[k], fabsf(g[6 * n + k]));
         }
     }
-    // hardware reciprocal (1 ulp): e stays within [-1, 1] up to that ulp, far below
-    // the half-precision step, and the decoder multiplies by smax itself
-    const float inv = smax > 0.0f ? __builtin_amdgcn_rcpf(smax) : 0.0f;
+    // per-shell scale (a half, rounded up) and its reciprocal: the hardware reciprocal
+    // (1 ulp) may put |e| a hair above 1, where the SNORM16 conversion saturates
+    _Float16 sh[6];
+    float inv[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        sh[k] = scale_half(smax[k]);
+        inv[k] = __builtin_amdgcn_rcpf((float)sh[k]);
+    }
     const unsigned uoff = (unsigned)off;
 #pragma unroll
     for (int n = 0; n < 12; ++n) {
@@ -924,18 +1094,21 @@ __device__ __forceinline__ void store_dev(void *fout, long long plane, int off, 
         u32x3 w;
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-            w[j] = scaled_f16x2(g[6 * n + 2 * j], g[6 * n + 2 * j + 1], inv);
+            const s16x2 q = __builtin_amdgcn_cvt_pknorm_i16(g[6 * n + 2 * j] * inv[2 * j],
+                                                            g[6 * n + 2 * j + 1] * inv[2 * j + 1]);
+            w[j] = __builtin_bit_cast(unsigned, q);
         }
         __builtin_amdgcn_raw_buffer_store_b96(w, r, uoff * 12u, 0u, STORE_POLICY);
     }
-    const rsrc_t rs = make_rsrc(base + 144LL * plane, 36u * (unsigned)plane);
-    const float sv[9] = {rho[0], rho[1], rho[2], rho[3], rho[4], rho[5], alpha, beta, smax};
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        const u32x3 w = {__builtin_bit_cast(unsigned, sv[3 * j]), __builtin_bit_cast(unsigned, sv[3 * j + 1]),
-                         __builtin_bit_cast(unsigned, sv[3 * j + 2])};
-        __builtin_amdgcn_raw_buffer_store_b96(w, rs, uoff * 36u, (unsigned)j * 12u, STORE_POLICY);
-    }
+    const rsrc_t rs = make_rsrc(base + 144LL * plane, 48u * (unsigned)plane);
+    const u32x4 s0 = {float_as_u32(rho[0]), float_as_u32(rho[1]), float_as_u32(rho[2]), float_as_u32(rho[3])};
+    const u32x4 s1 = {float_as_u32(rho[4]), float_as_u32(rho[5]), float_as_u32(alpha), float_as_u32(beta)};
+    const f16x2 h01 = {sh[0], sh[1]}, h23 = {sh[2], sh[3]}, h45 = {sh[4], sh[5]};
+    const u32x4 s2 = {__builtin_bit_cast(unsigned, h01), __builtin_bit_cast(unsigned, h23),
+                      __builtin_bit_cast(unsigned, h45), 0u};
+    __builtin_amdgcn_raw_buffer_store_b128(s0, rs, uoff * 48u, 0u, STORE_POLICY);
+    __builtin_amdgcn_raw_buffer_store_b128(s1, rs, uoff * 48u, 16u, STORE_POLICY);
+    __builtin_amdgcn_raw_buffer_store_b128(s2, rs, uoff * 48u, 32u, STORE_POLICY);
 }
 
 __device__ __forceinline__ void report(unsigned *status, unsigned flags) {
@@ -945,24 +1118,45 @@ __device__ __forceinline__ void report(unsigned *status, unsigned flags) {
 // ---------------------------------------------------------------- kernels
 // One fused update of cell (x, y) of the grid described by a.
 // FORCED: the variant for forced flows and RLBM_BC_WALL_NEQ rows (Sec. 3.4).
-template <int ST, typename S, typename R, int N = 5, bool FORCED = false>
-__device__ __forceinline__ void step_cell(const KArgs &a, int x, int y) {
-    unsigned flags = 0;
-    const bool wall_lo = (a.bc_xlo == RLBM_BC_WALL_T) && x == 0;
-    const bool wall_hi = (a.bc_xhi == RLBM_BC_WALL_T) && x == a.nx - 1;
-    const int xe = wall_lo ? 1 : (wall_hi ? a.nx - 2 : x);   // wall cells read their fluid neighbour
-    bool neq_lo = false, neq_hi = false;
-    int ye = y;
+// Where cell (x, y) pulls from: wall cells (fixed-temperature columns, and for the
+// forced variant the non-equilibrium wall rows) take the pull of their fluid neighbour.
+struct CellPlan {
+    bool wall_lo, wall_hi, neq_lo, neq_hi;
+    int xe, ye;
+};
+
+template <bool FORCED>
+__device__ __forceinline__ CellPlan plan_cell(const KArgs &a, int x, int y) {
+    CellPlan c;
+    c.wall_lo = (a.bc_xlo == RLBM_BC_WALL_T) && x == 0;
+    c.wall_hi = (a.bc_xhi == RLBM_BC_WALL_T) && x == a.nx - 1;
+    c.xe = c.wall_lo ? 1 : (c.wall_hi ? a.nx - 2 : x);   // wall cells read their fluid neighbour
+    c.neq_lo = c.neq_hi = false;
+    c.ye = y;
     if constexpr (FORCED) {
-        neq_lo = (a.bc_ylo == RLBM_BC_WALL_NEQ) && y == 0;
-        neq_hi = (a.bc_yhi == RLBM_BC_WALL_NEQ) && y == a.ny - 1;
-        ye = neq_lo ? 1 : (neq_hi ? a.ny - 2 : y);   // wall rows update their fluid neighbour first
+        c.neq_lo = (a.bc_ylo == RLBM_BC_WALL_NEQ) && y == 0;
+        c.neq_hi = (a.bc_yhi == RLBM_BC_WALL_NEQ) && y == a.ny - 1;
+        c.ye = c.neq_lo ? 1 : (c.neq_hi ? a.ny - 2 : y);   // wall rows update their fluid neighbour first
     }
+    return c;
+}
+
+template <typename S, typename R, int ST>
+__device__ __forceinline__ void pull_cell(const KArgs &a, const CellPlan &c, R (&f)[72]) {
     int xl, xr, yd, yu;
-    neighbours(a, xe, ye, xl, xr, yd, yu);
-    R f[72];
-    if constexpr (std::is_same<S, Dev16>::value) pull_dev<ST>(a.fin, a.plane, a.nx, xe, ye, xl, xr, yd, yu, f);
-    else pull<S, R>((const S *)a.fin, a.plane, a.nx, xe, ye, xl, xr, yd, yu, f);
+    neighbours(a, c.xe, c.ye, xl, xr, yd, yu);
+    if constexpr (std::is_same<S, Dev16>::value) pull_dev<ST>(a.fin, a.plane, a.nx, c.xe, c.ye, xl, xr, yd, yu, f);
+    else pull<S, R>((const S *)a.fin, a.plane, a.nx, c.xe, c.ye, xl, xr, yd, yu, f);
+}
+
+// Everything after the pull: moments, Landau frame, inversion, tau, equilibrium,
+// relaxation (or the wall rules), store.
+template <int ST, typename S, typename R, int N = 5, bool FORCED = false>
+__device__ __forceinline__ void finish_cell(const KArgs &a, int x, int y, const CellPlan &c, R (&f)[72]) {
+    unsigned flags = 0;
+    const bool wall_lo = c.wall_lo, wall_hi = c.wall_hi, neq_lo = c.neq_lo, neq_hi = c.neq_hi;
+    (void)neq_lo;
+    (void)neq_hi;
     const Mom m = moments<ST, R, std::is_same<S, Dev16>::value>(f);
     Macro M;
     int iters;
@@ -1013,10 +1207,50 @@ __device__ __forceinline__ void step_cell(const KArgs &a, int x, int y) {
 }
 
 template <int ST, typename S, typename R, int N = 5, bool FORCED = false>
+__device__ __forceinline__ void step_cell(const KArgs &a, int x, int y) {
+    const CellPlan c = plan_cell<FORCED>(a, x, y);
+    R f[72];
+    pull_cell<S, R, ST>(a, c, f);
+    finish_cell<ST, S, R, N, FORCED>(a, x, y, c, f);
+}
+
+// One tile of 16-bit deviation populations with the staged pull.  All threads of the
+// workgroup take part in the staging (its barriers); cells outside the grid stop after
+// it.  A wall cell whose fluid neighbour's stencil falls outside the halo tile (the
+// high x wall when a tile starts on it) pulls directly, with the same arithmetic.
+template <int ST>
+__device__ __forceinline__ void dev16_tile(const KArgs &a, int txi, int tyi, float *lds) {
+    const int x0 = txi * a.tx, y0 = tyi * a.ty;
+    const int lx = (int)threadIdx.x % a.tx, ly = (int)threadIdx.x / a.tx;
+    const int x = x0 + lx, y = y0 + ly;
+    const bool active = x < a.nx && y < a.ny;
+    const CellPlan c = plan_cell<false>(a, x, y);
+    const int hx = c.xe - x0 + 1, hy = c.ye - y0 + 1;
+    const bool inside = hx >= 1 && hx <= a.tx && hy >= 1 && hy <= a.ty;
+    float f[72];
+    dev_tile_pull<ST>(a, x0, y0, lds, hx, hy, active && inside, f);
+    if (!active) return;
+    if (!inside) pull_cell<Dev16, float, ST>(a, c, f);
+    finish_cell<ST, Dev16, float, 5, false>(a, x, y, c, f);
+}
+
+template <int ST, typename S, typename R, int N = 5, bool FORCED = false>
 __global__ RLBM_STEP_BOUNDS(ST, R, FORCED) void k_step(KArgs a) {
     int x, y;
     if (!cell_of(a, x, y)) return;
     step_cell<ST, S, R, N, FORCED>(a, x, y);
+}
+
+// Staged-pull step of 16-bit deviation populations (tiles with at most
+// DEV16_MAX_HALO halo cells); dynamic LDS: 2 x 6 floats per halo cell.
+template <int ST>
+__global__ RLBM_STEP_BOUNDS(ST, float, false) void k_step_dev16(KArgs a) {
+    extern __shared__ float dev16_lds[];
+    const int b = blockIdx.x;
+    const int t = (b & 7) * a.per_xcd + (b >> 3);
+    if (t >= a.ntiles) return;                 // the whole workgroup leaves together
+    const int tyi = t / a.ntx;
+    dev16_tile<ST>(a, t - tyi * a.ntx, tyi, dev16_lds);
 }
 
 // Many grids in one launch.  The tiles of all grids are numbered consecutively
@@ -1028,6 +1262,7 @@ struct Batch {
     int ntiles;
     int per_xcd;        // ceil(ntiles / 8)
     int groups_per_xcd; // workgroups launched per XCD
+    int staged;         // 16-bit deviations: staged pull (dynamic LDS sized for the tile)
 };
 
 template <int ST, typename S, typename R>
@@ -1045,6 +1280,16 @@ __global__ RLBM_BATCH_BOUNDS(ST, R) void k_step_batch(Batch b, const KArgs *__re
         const int lt = t - __builtin_amdgcn_readfirstlane(tile_base[g]);
         const int tyi = lt / a.ntx;
         const int txi = lt - tyi * a.ntx;
+        if constexpr (std::is_same<S, Dev16>::value) {
+            if (b.staged) {
+                extern __shared__ float dev16_lds[];
+                // no barrier between tiles: the buffers keep alternating by direction
+                // parity, so every read of a buffer ends before the next tile's
+                // barrier that precedes its rewrite
+                dev16_tile<ST>(a, txi, tyi, dev16_lds);
+                continue;
+            }
+        }
         const int x = txi * a.tx + (int)threadIdx.x % a.tx;
         const int y = tyi * a.ty + (int)threadIdx.x / a.tx;
         if (x < a.nx && y < a.ny) step_cell<ST, S, R>(a, x, y);
@@ -1065,6 +1310,13 @@ __global__ RLBM_STEP_BOUNDS(ST, R, false) void k_step_tiles(Batch b, const KArgs
     const int lt = t - __builtin_amdgcn_readfirstlane(tile_base[g]);
     const int tyi = lt / a.ntx;
     const int txi = lt - tyi * a.ntx;
+    if constexpr (std::is_same<S, Dev16>::value) {
+        if (b.staged) {
+            extern __shared__ float dev16_lds[];
+            dev16_tile<ST>(a, txi, tyi, dev16_lds);
+            return;
+        }
+    }
     const int x = txi * a.tx + (int)threadIdx.x % a.tx;
     const int y = tyi * a.ty + (int)threadIdx.x / a.tx;
     if (x < a.nx && y < a.ny) step_cell<ST, S, R>(a, x, y);
@@ -1197,6 +1449,7 @@ struct Kern {
         return prec == RLBM_FP64 ? k_step<ST, double, double>
              : prec == RLBM_FP32 ? k_step<ST, float, float> : k_step<ST, Dev16, float>;
     }
+    static KFn staged() { return k_step_dev16<ST>; }
     static BFn batch(int prec) {
         return prec == RLBM_FP64 ? k_step_batch<ST, double, double>
              : prec == RLBM_FP32 ? k_step_batch<ST, float, float> : k_step_batch<ST, Dev16, float>;
@@ -1256,6 +1509,18 @@ KFn pick_noneq(int st, int prec, int order) {
          : order == 4 ? noneq_kernel<RLBM_MJ, 4>(prec) : noneq_kernel<RLBM_MJ, 5>(prec);
 }
 
+KFn pick_staged(int st) {
+    return st == RLBM_MJ ? Kern<RLBM_MJ>::staged() : st == RLBM_FD ? Kern<RLBM_FD>::staged() : Kern<RLBM_BE>::staged();
+}
+
+// dynamic LDS of the staged 16-bit deviation pull for tiles of tx x ty, 0 if the
+// tile's halo is too large for it (those tiles pull directly)
+size_t staged_lds_bytes(int prec, int tx, int ty) {
+    const int nh = (tx + 2) * (ty + 2);
+    if (prec != RLBM_DEV16 || nh > DEV16_MAX_HALO) return 0;
+    return sizeof(float) * 12 * (size_t)nh;
+}
+
 BFn pick_batch(int st, int prec, bool persistent) {
     if (!persistent)
         return st == RLBM_MJ ? Kern<RLBM_MJ>::tiles(prec) : st == RLBM_FD ? Kern<RLBM_FD>::tiles(prec) : Kern<RLBM_BE>::tiles(prec);
@@ -1302,15 +1567,15 @@ int validate(const rlbm_params *p) {
     if (!p) return RLBM_EINVAL;
     if (p->nx < 2 || p->ny < 2) return RLBM_EINVAL;
     {
-        const long long elem = p->precision == RLBM_FP64 ? 8 : 4;   // F16DEV: its float side planes
-        const long long span = p->precision == RLBM_F16DEV ? 9 : 6;   // planes under one buffer descriptor
+        const long long elem = p->precision == RLBM_FP64 ? 8 : 4;   // DEV16: its 48-byte side records
+        const long long span = p->precision == RLBM_DEV16 ? 12 : 6;   // 4-byte planes under one buffer descriptor
         if (span * p->nx * p->ny * elem > 0xFFFFFFFFLL) return RLBM_EINVAL;
     }
     if (p->stats < RLBM_MJ || p->stats > RLBM_BE) return RLBM_EINVAL;
     if (p->order < 2 || p->order > 5) return RLBM_EINVAL;
-    if (p->order != 5 && (p->stats != RLBM_MJ || p->precision == RLBM_F16DEV))
+    if (p->order != 5 && (p->stats != RLBM_MJ || p->precision == RLBM_DEV16))
         return RLBM_ENOTIMPL;   // lower orders: Maxwell-Juttner with FP64 or FP32 populations
-    if (p->precision != RLBM_FP64 && p->precision != RLBM_FP32 && p->precision != RLBM_F16DEV) return RLBM_EINVAL;
+    if (p->precision != RLBM_FP64 && p->precision != RLBM_FP32 && p->precision != RLBM_DEV16) return RLBM_EINVAL;
     if (p->tau_mode == RLBM_TAU_CONST) {
         if (!(p->tau > 0.5)) return RLBM_EINVAL;   // gamma (1 + |u|)/2 >= 1/2: unstable for every state
     } else if (p->tau_mode == RLBM_TAU_INV_THETA) {
@@ -1323,7 +1588,7 @@ int validate(const rlbm_params *p) {
     if (p->bc[0] == RLBM_BC_WALL_NEQ || p->bc[1] == RLBM_BC_WALL_NEQ) return RLBM_EINVAL;   // y sides only
     if (!std::isfinite(p->force[0]) || !std::isfinite(p->force[1])) return RLBM_EINVAL;
     if (is_forced(*p)) {
-        if (p->order != 5 || p->precision == RLBM_F16DEV) return RLBM_ENOTIMPL;
+        if (p->order != 5 || p->precision == RLBM_DEV16) return RLBM_ENOTIMPL;
         if ((p->bc[2] == RLBM_BC_WALL_NEQ || p->bc[3] == RLBM_BC_WALL_NEQ) &&
             (p->ny < 3 || !(p->wall_n > 0.0) || !(p->wall_theta > 0.0)))
             return RLBM_EINVAL;
@@ -1469,14 +1734,22 @@ int launch_step(rlbm_ctx *c, hipStream_t s) {
         b.groups_per_xcd = c->batch_groups_per_xcd;
         const KArgs *descs = c->d_descs + (size_t)c->cur * c->base.size();
         const bool persistent = b.groups_per_xcd < b.per_xcd;
-        hipLaunchKernelGGL(pick_batch(p0.stats, p0.precision, persistent), dim3(8 * b.groups_per_xcd), dim3(256), 0, s, b,
-                           descs, (const int *)c->d_tile_grid, (const int *)c->d_tile_base);
+        const size_t lds = staged_lds_bytes(p0.precision, c->tx, c->ty);
+        b.staged = lds > 0;
+        hipLaunchKernelGGL(pick_batch(p0.stats, p0.precision, persistent), dim3(8 * b.groups_per_xcd), dim3(256), lds, s,
+                           b, descs, (const int *)c->d_tile_grid, (const int *)c->d_tile_base);
     } else {
         KArgs a = c->base[0];
         a.fin = c->cur ? p0.f_b : p0.f_a;
         a.fout = c->cur ? p0.f_a : p0.f_b;
-        const KFn k = is_forced(p0) ? pick_forced(p0.stats, p0.precision) : pick_order(0, p0.stats, p0.precision, p0.order);
-        hipLaunchKernelGGL(k, dim3(8 * a.per_xcd), dim3(256), 0, s, a);
+        const size_t lds = staged_lds_bytes(p0.precision, c->tx, c->ty);
+        if (lds > 0) {
+            // 16-bit deviations are order 5 without forcing (checked at create)
+            hipLaunchKernelGGL(pick_staged(p0.stats), dim3(8 * a.per_xcd), dim3(256), lds, s, a);
+        } else {
+            const KFn k = is_forced(p0) ? pick_forced(p0.stats, p0.precision) : pick_order(0, p0.stats, p0.precision, p0.order);
+            hipLaunchKernelGGL(k, dim3(8 * a.per_xcd), dim3(256), 0, s, a);
+        }
     }
     c->cur ^= 1;
     c->steps++;

@@ -14,12 +14,12 @@ LIB_PATH = os.path.join(HERE, "librlbm.so")
 
 RLBM_OK, RLBM_EINVAL, RLBM_EDOMAIN, RLBM_EHIP, RLBM_ENONFINITE, RLBM_ENOTIMPL = 0, -1, -2, -3, -4, -5
 STATS = {"MJ": 0, "FD": 1, "BE": 2}
-PRECISION = {"fp64": 0, "fp32": 1, "f16dev": 2}
+PRECISION = {"fp64": 0, "fp32": 1, "dev16": 2}
 TAU_MODE = {"const": 0, "theta": 1}
 BC = {"periodic": 0, "open": 1, "wall": 2, "wall_neq": 3}
 GUESS = {"fixed": 0, "mlp": 1}
 DTYPE = {"fp64": torch.float64, "fp32": torch.float32}
-F16DEV_BYTES_PER_CELL = 180   # 72 half deviations + 9 float side values
+DEV16_BYTES_PER_CELL = 192   # 72 SNORM16 deviations + 8 float side values + 6 half scales + padding
 FIELD_NAMES = ("n", "eps", "theta", "z", "ux", "uy", "qx", "qy")
 MOMENT_NAMES = ("N0", "Nx", "Ny", "T00", "T0x", "T0y", "Txx", "Txy", "Tyy")
 
@@ -113,7 +113,7 @@ def unpack_populations(buf, precision, nx, ny):
     elif precision == "fp64":
         rec = blk.reshape(12, 3, P, 2).permute(0, 2, 1, 3).reshape(12, P, 6)
     else:
-        raise ValueError("FP16-deviation buffers: use f16dev_views")
+        raise ValueError("16-bit deviation buffers: use dev16_views")
     return rec.permute(0, 2, 1).reshape(72, ny, nx).contiguous()
 
 
@@ -144,8 +144,8 @@ def _grid_args(params, init, device, stream):
     """Population buffers, rlbm_params and rlbm_init_fields for one grid."""
     nx, ny = int(params["nx"]), int(params["ny"])
     prec = params.get("precision", "fp64")
-    if prec == "f16dev":
-        f = [torch.empty(F16DEV_BYTES_PER_CELL * nx * ny // 4, dtype=torch.float32, device=device) for _ in range(2)]
+    if prec == "dev16":
+        f = [torch.empty(DEV16_BYTES_PER_CELL * nx * ny // 4, dtype=torch.float32, device=device) for _ in range(2)]
     else:
         f = [torch.empty(72 * nx * ny, dtype=DTYPE[prec], device=device) for _ in range(2)]
     bc = params.get("bc", ("periodic",) * 4)
@@ -173,7 +173,7 @@ class Sim:
     """One grid: owns two population tensors (ping-pong) on the current CUDA/HIP device.
 
     params: dict with keys nx, ny, stats ('MJ'|'FD'|'BE'), order (2..5, default 5),
-    precision ('fp64'|'fp32'|'f16dev'), tau_mode ('const'|'theta'), tau, tau_a, tau_b,
+    precision ('fp64'|'fp32'|'dev16'), tau_mode ('const'|'theta'), tau, tau_a, tau_b,
     bc (xlo, xhi, ylo, yhi names from BC), theta_wall (xlo, xhi), guess ('fixed'|'mlp')
     with mlp (the network's weight tensor), tile ((tile_x, tile_y), default automatic),
     collect_stats, force ((a_x, a_y), momentum update), wall_n and wall_theta (state
@@ -279,15 +279,18 @@ class Sim:
             pass
 
 
-def f16dev_views(buf, nx, ny):
-    """(deviations (72, ny, nx) float16 with q = 6 n + k, side values (9, ny, nx)
-    float32) of an RLBM_F16DEV buffer, rearranged from its cell-packed layout
-    (12 direction blocks of cells x 6 halves, then cells x 9 floats); copies."""
+def dev16_views(buf, nx, ny):
+    """(deviations (72, ny, nx) int16 with q = 6 n + k, side values (8, ny, nx) float32
+    rho_0..rho_5, alpha, beta, shell scales (6, ny, nx) float16) of an RLBM_DEV16 buffer,
+    rearranged from its cell-packed layout (12 direction blocks of cells x 6 SNORM16,
+    then cells x 48-byte side records); copies."""
     raw = buf.view(torch.uint8)
     P = nx * ny
-    dev = raw[: 144 * P].view(torch.float16).view(12, ny, nx, 6).permute(0, 3, 1, 2).reshape(72, ny, nx)
-    side = raw[144 * P: 180 * P].view(torch.float32).view(ny, nx, 9).permute(2, 0, 1).contiguous()
-    return dev, side
+    dev = raw[: 144 * P].view(torch.int16).view(12, ny, nx, 6).permute(0, 3, 1, 2).reshape(72, ny, nx)
+    rec = raw[144 * P: 192 * P].view(ny, nx, 48)
+    side = rec[:, :, :32].contiguous().view(torch.float32).permute(2, 0, 1).contiguous()
+    scale = rec[:, :, 32:44].contiguous().view(torch.float16).permute(2, 0, 1).contiguous()
+    return dev.contiguous(), side, scale
 
 
 class GuessNet:

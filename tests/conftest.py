@@ -24,3 +24,10 @@ def read_golden(name):
                 continue
             rows.append(line.split())
     return rows
+
+
+def same_bits(a, b):
+    """Bitwise equality of two population buffers (16-bit deviation buffers hold int16
+    pairs whose float32 view can be a NaN pattern, which torch.equal never matches)."""
+    import torch
+    return a.shape == b.shape and torch.equal(a.contiguous().view(torch.int32), b.contiguous().view(torch.int32))

@@ -7,6 +7,7 @@ import pytest
 import torch
 
 import workloads
+from conftest import same_bits
 from oracle import lattice as L
 
 pytestmark = pytest.mark.gpu
@@ -80,7 +81,7 @@ def test_graph_replay_matches_eager(rl):
             e.step(1)                   # eager launches
         fa = a.fields()                 # eager work between replays
         torch.cuda.synchronize()
-        assert torch.equal(a.state(), e.state()), rep
+        assert same_bits(a.state(), e.state()), rep
         assert torch.equal(fa["theta"], e.fields()["theta"]), rep
     a.close()
     e.close()
@@ -95,7 +96,7 @@ def test_batch_graph_replay_matches_eager(rl):
         for _ in range(96):
             e.step(1)
         for i in range(len(grids)):
-            assert torch.equal(a.state(i), e.state(i)), (rep, i)
+            assert same_bits(a.state(i), e.state(i)), (rep, i)
     a.close()
     e.close()
 
@@ -110,7 +111,7 @@ def test_autotune_keeps_results(rl):
     ref = mk()
     ref.step(n_done)
     for i in range(len(grids)):
-        assert torch.equal(a.state(i), ref.state(i)), i
+        assert same_bits(a.state(i), ref.state(i)), i
     a.close()
     ref.close()
 
@@ -168,14 +169,18 @@ def test_fourier_conductivity_on_gpu(rl):
 TILES = [(32, 8), (64, 4), (128, 2), (256, 1), (16, 16)]
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32", "f16dev"])
-def test_results_do_not_depend_on_the_tile(rl, precision):
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "dev16"])
+@pytest.mark.parametrize("nx", [37, 33])
+def test_results_do_not_depend_on_the_tile(rl, precision, nx):
     """Every cell's update is the same arithmetic whatever tile covers it: each tile
-    shape (ragged in x and y on this 37 x 11 grid, walls on x) gives the same bits."""
-    p, f = workloads.fourier(nx=37, ny=11, dT=0.04, tau=0.85)
+    shape (ragged in x and y on these nx x 11 grids, walls on x) gives the same bits.
+    For 16-bit deviations the tiles with at most 512 halo cells take the staged pull
+    and the others the direct one; at nx = 33 a 32-wide tile starts at the hot wall
+    cell, whose stencil lies outside its halo and is pulled directly."""
+    p, f = workloads.fourier(nx=nx, ny=11, dT=0.04, tau=0.85)
     p = dict(p, stats="FD", precision=precision)
-    f = workloads.smooth_random(37, 11, seed=21, stats="FD", amp_u=0.1)
-    print(f"[tiles] FD 37x11 walls {precision}: {len(TILES)} tile shapes, 7 steps", flush=True)
+    f = workloads.smooth_random(nx, 11, seed=21, stats="FD", amp_u=0.1)
+    print(f"[tiles] FD {nx}x11 walls {precision}: {len(TILES)} tile shapes, 7 steps", flush=True)
     ref = None
     for t in TILES:
         s = rl.Sim(dict(p, tile=t), {k: v.cuda() for k, v in f.items()})
@@ -186,19 +191,21 @@ def test_results_do_not_depend_on_the_tile(rl, precision):
         if ref is None:
             ref = st
         else:
-            assert torch.equal(st, ref), t
+            assert same_bits(st, ref), t
 
 
-def test_batch_launch_modes_agree(rl):
-    """One workgroup per tile and the persistent sweep, for every tile shape: within
-    a launch mode the bits are the same; the two modes are separate kernels (their
-    own register budgets and instruction schedules) and agree to FP32 rounding."""
-    grids = _grids(stats="MJ", precision="fp32")
+@pytest.mark.parametrize("precision", ["fp32", "dev16"])
+def test_batch_launch_modes_agree(rl, precision):
+    """One workgroup per tile and the persistent sweep, for every tile shape, give the
+    same bits: the two modes are separate kernels (their own register budgets and
+    instruction schedules) over the same arithmetic, and a*b + c is fused only within
+    one source expression, so no kernel rounds differently."""
+    grids = _grids(stats="MJ", precision=precision)
     b = rl.Batch([g[0] for g in grids], [{k: v.cuda() for k, v in g[1].items()} for g in grids])
     b.step(5)
     saved = [b.state(i).clone() for i in range(len(grids))]
     ref = {}
-    print(f"[batch] {len(TILES)} tile shapes x 2 launch modes, 4 steps", flush=True)
+    print(f"[batch] {precision}: {len(TILES)} tile shapes x 2 launch modes, 4 steps", flush=True)
     for persistent in (0, 96):
         for t in TILES:
             for i in range(len(grids)):
@@ -210,8 +217,7 @@ def test_batch_launch_modes_agree(rl):
                 ref[persistent] = out
             else:
                 for i in range(len(grids)):
-                    assert torch.equal(out[i], ref[persistent][i]), (t, persistent, i)
+                    assert same_bits(out[i], ref[persistent][i]), (t, persistent, i)
     for i in range(len(grids)):
-        a, c = ref[0][i], ref[96][i]
-        assert (a - c).abs().max().item() <= 1e-6 * c.abs().max().item(), i
+        assert same_bits(ref[0][i], ref[96][i]), i
     b.close()

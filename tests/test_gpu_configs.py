@@ -1,7 +1,7 @@
 """The five workloads at their own sizes and step counts, measured through the C ABI.
 
 * FD hot spot 2048^2, 20000 steps, and BE hot spot 8192^2, 5000 steps: FP32 (fixed
-  inversion start) and FP16 deviations with the network guess against the library's
+  inversion start) and 16-bit deviations with the network guess against the library's
   FP64 path, which the parity tests tie to the oracle.  Norms of Sec. 3.5:
   eps_theta = sum|theta - theta_64| / sum theta_64 and eps_q = sum|q - q_64| / sum|q_64|
   over both components and the whole grid; n, eps, theta, z as max-norm relative
@@ -87,7 +87,7 @@ def _reduced_precision_errors(rl, make, make_train, steps, label):
     ref, st = _run_fields(rl, dict(params, precision="fp64"), fields, steps, f"{label} FP64")
     assert st == 0
     res = {}
-    for prec, guess in (("fp32", "fixed"), ("f16dev", "mlp")):
+    for prec, guess in (("fp32", "fixed"), ("dev16", "mlp")):
         p = dict(params, precision=prec)
         if guess == "mlp":
             p.update(guess="mlp", mlp=net.w)

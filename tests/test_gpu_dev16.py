@@ -1,5 +1,5 @@
-"""FP16 deviation storage (RLBM_F16DEV): populations stored as half-precision
-deviations from a per-cell dipole reference with a per-cell scale.  Checked
+"""16-bit deviation storage (RLBM_DEV16): populations stored as SNORM16 deviations
+from a per-cell dipole reference with a scale per radial shell.  Checked
 against the FP64 oracle (fields after a few steps), against the library's own FP64
 path on the hot spot with the paper's error norms (Sec. 3.5: eps_theta, eps_q), and
 its storage layout decoded on the host."""
@@ -8,6 +8,8 @@ import pytest
 import torch
 
 import workloads
+from conftest import same_bits
+from dev16 import decode, quantum
 from oracle import lattice as L
 from oracle import quadrature as Q
 
@@ -22,30 +24,22 @@ def rl():
     return rlbm
 
 
-def decode(rl, buf, nx, ny, stats):
-    """Host decoding of an F16DEV buffer: f_i = w_k (R_i + s e_i)."""
-    dev, side = rl.f16dev_views(buf, nx, ny)
-    e = dev.double().cpu().numpy()
-    sd = side.double().cpu().numpy()
-    v = Q.vectors(stats)
-    R = sd[v["k"]] + v["p0"][:, None, None] * (sd[6] * v["vx"][:, None, None] + sd[7] * v["vy"][:, None, None])
-    return v["w"][:, None, None] * (R + sd[8] * e)
-
-
 WALLS = dict(bc=("wall", "wall", "open", "open"), theta_wall=(0.93, 1.06), tau_mode="theta", tau_a=0.5, tau_b=0.6)
 
 
 @pytest.mark.parametrize("stats,nsteps,setup", [("MJ", 6, "periodic"), ("FD", 4, "periodic"), ("BE", 4, "periodic"),
                                                 ("MJ", 5, "walls"), ("FD", 4, "walls"), ("BE", 4, "walls")])
-def test_f16dev_against_oracle(rl, stats, nsteps, setup):
+def test_dev16_against_oracle(rl, stats, nsteps, setup):
     nx, ny = 70, 13
     fields = workloads.smooth_random(nx, ny, seed=31, stats=stats)
     extra = WALLS if setup == "walls" else {}
-    print(f"[f16dev] {stats} {nx}x{ny} {setup} {nsteps} steps vs oracle", flush=True)
-    sim = rl.Sim(dict(nx=nx, ny=ny, stats=stats, precision="f16dev", tau=0.9, **extra),
+    print(f"[dev16] {stats} {nx}x{ny} {setup} {nsteps} steps vs oracle", flush=True)
+    sim = rl.Sim(dict(nx=nx, ny=ny, stats=stats, precision="dev16", tau=0.9, **extra),
                  {k: v.cuda() for k, v in fields.items()})
-    # the initial state decodes to the equilibrium within the half-precision rounding
-    # of the scaled deviation: |f - f_eq| <= w_k s 2^-11 (plus FP32 rounding of f_eq)
+    # the initial state decodes to the equilibrium within about half a SNORM16 step of
+    # the shell's scale, w_k s_k / (2 * 32767) (plus FP32 rounding of f_eq); the
+    # hardware's float -> SNORM16 conversion is allowed 0.6 of a step (as graphics APIs
+    # allow), and the test takes that
     f0 = decode(rl, sim.state(), nx, ny, stats)
     if setup == "walls":
         op = L.Params(stats=stats, nx=nx, ny=ny, tau_mode="theta", tau_a=0.5, tau_b=0.6,
@@ -54,10 +48,7 @@ def test_f16dev_against_oracle(rl, stats, nsteps, setup):
     else:
         op = L.Params(stats=stats, nx=nx, ny=ny, tau=0.9)
     ref0 = L.init_state(op, fields["theta"].numpy(), fields["ux"].numpy(), fields["uy"].numpy(), z=fields["z"].numpy())
-    _, side = rl.f16dev_views(sim.state(), nx, ny)
-    s = side[8].double().cpu().numpy()
-    w = Q.vectors(stats)["w"][:, None, None]
-    bound = w * s * 2.0 ** -11 * 1.01 + 2e-6 * np.abs(ref0)
+    bound = quantum(rl, sim.state(), nx, ny, stats) * 1.2 + 2e-6 * np.abs(ref0)
     worst = (np.abs(f0 - ref0) / bound).max()
     print(f"  {stats}: initial decode error / bound = {worst:.2f}")
     assert worst <= 1.0
@@ -75,19 +66,19 @@ def test_f16dev_against_oracle(rl, stats, nsteps, setup):
         assert err <= tol, (key, err)
 
 
-def test_f16dev_hotspot_error_norms(rl):
-    """Fermi-Dirac hot spot (256^2, amp 0.3, sigma 8), 400 steps: F16DEV and FP32
+def test_dev16_hotspot_error_norms(rl):
+    """Fermi-Dirac hot spot (256^2, amp 0.3, sigma 8), 400 steps: DEV16 and FP32
     against the FP64 path of the same library, with the paper's norms
     eps_theta = sum|dtheta| / sum theta and eps_q = sum|dq| / sum|q|."""
     params, fields = workloads.hotspot_fd(L=256, seed=4, sigma=8.0)
     out = {}
-    for prec in ("fp64", "fp32", "f16dev"):
+    for prec in ("fp64", "fp32", "dev16"):
         sim = rl.Sim(dict(params, precision=prec), {k: v.cuda() for k, v in fields.items()})
         sim.step(400)
         out[prec] = {k: v.cpu().numpy() for k, v in sim.fields().items()}
         sim.close()
     ref = out["fp64"]
-    for prec in ("fp32", "f16dev"):
+    for prec in ("fp32", "dev16"):
         r = out[prec]
         et = np.abs(r["theta"] - ref["theta"]).sum() / ref["theta"].sum()
         eq = (np.abs(r["qx"] - ref["qx"]).sum() + np.abs(r["qy"] - ref["qy"]).sum()) / \
@@ -96,15 +87,15 @@ def test_f16dev_hotspot_error_norms(rl):
         assert et <= 1e-3 and eq <= 1e-3, (prec, et, eq)
 
 
-def test_f16dev_batch_matches_single(rl):
-    specs = [(dict(nx=40, ny=9, stats="FD", precision="f16dev", tau=0.8), workloads.smooth_random(40, 9, 1, "FD")),
-             (dict(nx=33, ny=17, stats="FD", precision="f16dev", tau=1.1, bc=("open",) * 4),
+def test_dev16_batch_matches_single(rl):
+    specs = [(dict(nx=40, ny=9, stats="FD", precision="dev16", tau=0.8), workloads.smooth_random(40, 9, 1, "FD")),
+             (dict(nx=33, ny=17, stats="FD", precision="dev16", tau=1.1, bc=("open",) * 4),
               workloads.smooth_random(33, 17, 2, "FD"))]
     b = rl.Batch([s[0] for s in specs], [{k: v.cuda() for k, v in s[1].items()} for s in specs])
     b.step(7)
     for i, (p, f) in enumerate(specs):
         s = rl.Sim(p, {k: v.cuda() for k, v in f.items()})
         s.step(7)
-        assert torch.equal(b.state(i), s.state()), i
+        assert same_bits(b.state(i), s.state()), i
         s.close()
     b.close()

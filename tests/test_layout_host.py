@@ -1,6 +1,6 @@
 """Host-side conversion between (72, ny, nx) populations and the library's buffer
 layouts (no GPU): FP32/FP64 cell records per direction block, and the FP16-deviation
-buffer's rearranged views.  Layout as documented in include/rlbm.h."""
+buffer's rearranged views (SNORM16 deviations, side values, half scales).  Layout as documented in include/rlbm.h."""
 import numpy as np
 import pytest
 import torch
@@ -33,18 +33,24 @@ def test_record_positions(precision, dtype):
         assert buf[idx] == f[6 * n + k, y, x]
 
 
-def test_f16dev_views_layout():
+def test_dev16_views_layout():
     nx, ny = 5, 3
     P = nx * ny
-    raw = torch.zeros(180 * P, dtype=torch.uint8)
-    dev = torch.arange(72 * P, dtype=torch.float16)          # exact in half precision
-    side = torch.arange(9 * P, dtype=torch.float32) + 0.5
+    raw = torch.zeros(192 * P, dtype=torch.uint8)
+    dev = torch.arange(72 * P, dtype=torch.int16) - 500
+    side = torch.arange(8 * P, dtype=torch.float32) + 0.5
+    scale = (torch.arange(6 * P, dtype=torch.float32) * 0.25).half()
     raw[:144 * P] = dev.view(torch.uint8)
-    raw[144 * P:] = side.view(torch.uint8)
-    d, s = rlbm.f16dev_views(raw.view(torch.float32), nx, ny)
+    rec = raw[144 * P:].view(P, 48)
+    rec[:, :32] = side.view(P, 8).contiguous().view(torch.uint8).view(P, 32)
+    rec[:, 32:44] = scale.view(P, 6).contiguous().view(torch.uint8).view(P, 12)
+    d, s, sc = rlbm.dev16_views(raw.view(torch.float32), nx, ny)
     for n, k, x, y in [(0, 0, 0, 0), (4, 5, 3, 2), (11, 1, 4, 1)]:
         c = y * nx + x
         assert d[6 * n + k, y, x] == dev[n * 6 * P + 6 * c + k]
-    for j, x, y in [(0, 0, 0), (8, 4, 2), (5, 2, 1)]:
+    for j, x, y in [(0, 0, 0), (7, 4, 2), (5, 2, 1)]:
         c = y * nx + x
-        assert s[j, y, x] == side[9 * c + j]
+        assert s[j, y, x] == side[8 * c + j]
+    for j, x, y in [(0, 0, 0), (5, 4, 2), (3, 2, 1)]:
+        c = y * nx + x
+        assert sc[j, y, x] == scale[6 * c + j]
