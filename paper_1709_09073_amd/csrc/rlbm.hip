@@ -1038,14 +1038,71 @@ __device__ __forceinline__ _Float16 scale_half(float s) { return (_Float16)fmaf(
 
 typedef short s16x2 __attribute__((ext_vector_type(2)));
 
+// Sum over the 12 directions of c_n v_n and s_n v_n from the differences
+// d_n = v_n - v_{n+6} of opposite directions (cos phi_n = 1, S3H, 1/2, 0, -1/2, -S3H and
+// sin phi_n = 0, 1/2, S3H, 1, S3H, 1/2 for n = 0..5).
+__device__ __forceinline__ float dipole_c(const float (&d)[6]) {
+    return d[0] + (float)S3H * (d[1] - d[5]) + 0.5f * (d[2] - d[4]);
+}
+__device__ __forceinline__ float dipole_s(const float (&d)[6]) {
+    return d[3] + 0.5f * (d[1] + d[5]) + (float)S3H * (d[2] + d[4]);
+}
+
+// The same sums with sqrt(3)/2 carried as two floats (hi + lo), so the constant is
+// exact to FP64 and only the arithmetic rounds: these sums feed a correction applied
+// in every cell and step, and a constant off by 2e-8 would bias it the same way each
+// time.
+constexpr float S3H_HI = (float)S3H;
+constexpr float S3H_LO = (float)(S3H - (double)S3H_HI);
+__device__ __forceinline__ float dipole_c_exact(const float (&d)[6]) {
+    const float a = d[1] - d[5];
+    return fmaf(S3H_LO, a, fmaf(S3H_HI, a, fmaf(0.5f, d[2] - d[4], d[0])));
+}
+__device__ __forceinline__ float dipole_s_exact(const float (&d)[6]) {
+    const float a = d[2] + d[4];
+    return fmaf(S3H_LO, a, fmaf(S3H_HI, a, fmaf(0.5f, d[1] + d[5], d[3])));
+}
+
+// x / d with a rounding error of at most about half an ulp, either sign: x times the
+// rounded reciprocal c, then one correction by the exact residual x - d q.  (x * c
+// alone is off by the relative error of c, the same sign every time: applied to a
+// conserved density in every cell and step, that would be a steady drift.)
+__device__ __forceinline__ float div_by(float x, float d, float c) {
+    const float q = x * c;
+    return fmaf(fmaf(-q, d, x), c, q);
+}
+
+// Momentum density sum_q f p^0 p^x (weights, momenta and cosines exact) of the decoded
+// dipole p~_k (alpha c~_n + beta s~_n) per unit of alpha, where the decoder's p~_k, c~_n,
+// s~_n are the shell momenta, cosines and sines rounded to float:
+// sum_k W_k P_k^2 p~_k * sum_n c_n c~_n.  (sum_n c_n s~_n vanishes: the rounded values
+// keep the table's symmetry; the y sum is the same.)
+template <int ST>
+constexpr double dipole_moment_norm() {
+    double m = 0.0;
+    for (int k = 0; k < 6; ++k)
+        m += W_SHELL[ST][k] * P_SHELL[ST][k] * P_SHELL[ST][k] * (double)(float)P_SHELL[ST][k];
+    double c = 0.0;
+    for (int n = 0; n < 12; ++n) c += cdir(n) * (double)(float)cdir(n);
+    return m * c;
+}
+
+// Encode the populations g = f/w of one cell (post-collision) as 16-bit deviations.
+// The reference R_{k,n} = rho_k + p_k (alpha cos phi_n + beta sin phi_n) is the shell
+// average plus the least-squares dipole; each shell's deviations are coded against
+// its own maximum (a half, rounded up).  After coding, rho_k, alpha and beta are
+// corrected so that the decoded populations keep the cell's shell sums (so N^0 and
+// T^00) and its momentum density T^{0x}, T^{0y} exactly: the rounding errors of the
+// codes would otherwise act as a small random source of those conserved quantities in
+// every cell and step.
 template <int ST>
 __device__ __forceinline__ void store_dev(void *fout, long long plane, int off, const float (&f)[72]) {
     char *base = (char *)fout;
     float g[72];
 #pragma unroll
     for (int q = 0; q < 72; ++q) g[q] = f[q];
-    float rho[6], A = 0.0f, B = 0.0f;
-    double pp = 0.0;
+    float rho[6], shell_sum[6], A = 0.0f, B = 0.0f;
+    double pp = 0.0, X = 0.0, Y = 0.0;   // T^{0x}, T^{0y} (weights exact)
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
         // directions n and n + 6 are opposite: sums e_n = g_n + g_{n+6} enter the
@@ -1057,12 +1114,15 @@ __device__ __forceinline__ void store_dev(void *fout, long long plane, int off, 
             d[n] = g[6 * n + k] - g[6 * (n + 6) + k];
         }
         const float sum = ((e[0] + e[1]) + (e[2] + e[3])) + (e[4] + e[5]);
-        // cos phi_n = 1, S3H, 1/2, 0, -1/2, -S3H and sin phi_n = 0, 1/2, S3H, 1, S3H, 1/2
-        const float sc = d[0] + (float)S3H * (d[1] - d[5]) + 0.5f * (d[2] - d[4]);
-        const float ss = d[3] + 0.5f * (d[1] + d[5]) + (float)S3H * (d[2] + d[4]);
+        const float sc = dipole_c(d), ss = dipole_s(d);
+        shell_sum[k] = sum;
         rho[k] = sum * (1.0f / 12.0f);
-        A += (float)P_SHELL[ST][k] * sc;
-        B += (float)P_SHELL[ST][k] * ss;
+        const float p = (float)P_SHELL[ST][k];
+        const double wpp = W_SHELL[ST][k] * P_SHELL[ST][k] * P_SHELL[ST][k];
+        A = fmaf(p, sc, A);
+        B = fmaf(p, ss, B);
+        X = fma(wpp, (double)dipole_c_exact(d), X);
+        Y = fma(wpp, (double)dipole_s_exact(d), Y);
         pp += P_SHELL[ST][k] * P_SHELL[ST][k];
     }
     // least-squares dipole: sum_n cos^2 = 6 over the 12 directions
@@ -1088,6 +1148,7 @@ __device__ __forceinline__ void store_dev(void *fout, long long plane, int off, 
         inv[k] = __builtin_amdgcn_rcpf((float)sh[k]);
     }
     const unsigned uoff = (unsigned)off;
+    unsigned code[12][3];
 #pragma unroll
     for (int n = 0; n < 12; ++n) {
         const rsrc_t r = make_rsrc(base + (long long)n * plane * 12, 12u * (unsigned)plane);
@@ -1096,13 +1157,36 @@ __device__ __forceinline__ void store_dev(void *fout, long long plane, int off, 
         for (int j = 0; j < 3; ++j) {
             const s16x2 q = __builtin_amdgcn_cvt_pknorm_i16(g[6 * n + 2 * j] * inv[2 * j],
                                                             g[6 * n + 2 * j + 1] * inv[2 * j + 1]);
-            w[j] = __builtin_bit_cast(unsigned, q);
+            w[j] = code[n][j] = __builtin_bit_cast(unsigned, q);
         }
         __builtin_amdgcn_raw_buffer_store_b96(w, r, uoff * 12u, 0u, STORE_POLICY);
     }
+    // the codes' shell sums and dipole sums, and the corrections that restore the
+    // cell's conserved densities (the decoder's step is the half scale times 1/32767)
+    double DX = 0.0, DY = 0.0;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        float e[6], d[6];
+#pragma unroll
+        for (int n = 0; n < 6; ++n) {
+            const float a = dev_value(u32x3{code[n][0], code[n][1], code[n][2]}, k);
+            const float b = dev_value(u32x3{code[n + 6][0], code[n + 6][1], code[n + 6][2]}, k);
+            e[n] = a + b;
+            d[n] = a - b;
+        }
+        const float S = ((e[0] + e[1]) + (e[2] + e[3])) + (e[4] + e[5]);   // integer, exact
+        const float step = (float)sh[k] * SNORM16_STEP;
+        rho[k] = div_by(fmaf(-step, S, shell_sum[k]), 12.0f, 1.0f / 12.0f);
+        const double wpps = W_SHELL[ST][k] * P_SHELL[ST][k] * P_SHELL[ST][k] * (double)step;
+        DX = fma(wpps, (double)dipole_c_exact(d), DX);
+        DY = fma(wpps, (double)dipole_s_exact(d), DY);
+    }
+    // the decoded momentum density is alpha * dipole_moment_norm + DX: keep it at X
+    constexpr double inv_m3 = 1.0 / dipole_moment_norm<ST>();
+    const float alpha_c = (float)((X - DX) * inv_m3), beta_c = (float)((Y - DY) * inv_m3);
     const rsrc_t rs = make_rsrc(base + 144LL * plane, 48u * (unsigned)plane);
     const u32x4 s0 = {float_as_u32(rho[0]), float_as_u32(rho[1]), float_as_u32(rho[2]), float_as_u32(rho[3])};
-    const u32x4 s1 = {float_as_u32(rho[4]), float_as_u32(rho[5]), float_as_u32(alpha), float_as_u32(beta)};
+    const u32x4 s1 = {float_as_u32(rho[4]), float_as_u32(rho[5]), float_as_u32(alpha_c), float_as_u32(beta_c)};
     const f16x2 h01 = {sh[0], sh[1]}, h23 = {sh[2], sh[3]}, h45 = {sh[4], sh[5]};
     const u32x4 s2 = {__builtin_bit_cast(unsigned, h01), __builtin_bit_cast(unsigned, h23),
                       __builtin_bit_cast(unsigned, h45), 0u};

@@ -9,7 +9,7 @@ import torch
 
 import workloads
 from conftest import same_bits
-from dev16 import decode, quantum
+from dev16 import decode, decode_bound
 from oracle import lattice as L
 from oracle import quadrature as Q
 
@@ -36,10 +36,9 @@ def test_dev16_against_oracle(rl, stats, nsteps, setup):
     print(f"[dev16] {stats} {nx}x{ny} {setup} {nsteps} steps vs oracle", flush=True)
     sim = rl.Sim(dict(nx=nx, ny=ny, stats=stats, precision="dev16", tau=0.9, **extra),
                  {k: v.cuda() for k, v in fields.items()})
-    # the initial state decodes to the equilibrium within about half a SNORM16 step of
-    # the shell's scale, w_k s_k / (2 * 32767) (plus FP32 rounding of f_eq); the
-    # hardware's float -> SNORM16 conversion is allowed 0.6 of a step (as graphics APIs
-    # allow), and the test takes that
+    # the initial state decodes to the equilibrium within the coding bound (codes off
+    # by 0.6 of a SNORM16 step at most, plus the encoder's conserving correction of
+    # rho, alpha, beta; dev16.decode_bound), plus FP32 rounding of f_eq
     f0 = decode(rl, sim.state(), nx, ny, stats)
     if setup == "walls":
         op = L.Params(stats=stats, nx=nx, ny=ny, tau_mode="theta", tau_a=0.5, tau_b=0.6,
@@ -48,10 +47,24 @@ def test_dev16_against_oracle(rl, stats, nsteps, setup):
     else:
         op = L.Params(stats=stats, nx=nx, ny=ny, tau=0.9)
     ref0 = L.init_state(op, fields["theta"].numpy(), fields["ux"].numpy(), fields["uy"].numpy(), z=fields["z"].numpy())
-    bound = quantum(rl, sim.state(), nx, ny, stats) * 1.2 + 2e-6 * np.abs(ref0)
+    bound = decode_bound(rl, sim.state(), nx, ny, stats) + 2e-6 * np.abs(ref0)
     worst = (np.abs(f0 - ref0) / bound).max()
     print(f"  {stats}: initial decode error / bound = {worst:.2f}")
     assert worst <= 1.0
+    # the encoder keeps each shell's sum over the 12 directions (so N^0 and T^00) and the
+    # momentum density T^{0x}, T^{0y}: they agree with the oracle's equilibrium to FP32
+    # rounding, far below what the code steps alone would leave
+    v = Q.vectors(stats)
+    pc = (v["p0"] ** 2 * v["vx"])[:, None, None]
+    ps = (v["p0"] ** 2 * v["vy"])[:, None, None]
+    shell = lambda a: a.reshape(12, 6, ny, nx).sum(0)
+    for name, got0, want0, scale0 in (
+            ("shell sums", shell(f0), shell(ref0), shell(np.abs(ref0))),
+            ("T^0x", (pc * f0).sum(0), (pc * ref0).sum(0), (np.abs(pc * ref0)).sum(0)),
+            ("T^0y", (ps * f0).sum(0), (ps * ref0).sum(0), (np.abs(ps * ref0)).sum(0))):
+        rel = (np.abs(got0 - want0) / scale0).max()
+        print(f"  {stats}: {name} of the decoded state: {rel:.2e} relative", flush=True)
+        assert rel <= 2e-6, (name, rel)
     sim.step(nsteps)
     got = {k: v.cpu().numpy() for k, v in sim.fields().items()}
     sim.close()

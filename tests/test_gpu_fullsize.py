@@ -8,8 +8,9 @@ with the GPU's after its own next step.
 Bars are set on the scale of f_i / w_k, the variable the expansion works in: with
 M = max_i |f_i / w_k| of the oracle's result for the cell, FP32 populations must agree
 to 4e-6 w_k M (FP32 storage and arithmetic from the same FP32 inputs), 16-bit
-deviations to 0.6 of a SNORM16 step of the new state, 1.2 w_k s_k / (2 * 32767), plus
-4e-6 w_k M (0.6 of a step: the tolerance graphics APIs give float -> SNORM16 conversion).
+deviations to the coding bound of the new state (codes within 0.6 of a SNORM16 step,
+the tolerance graphics APIs give float -> SNORM16 conversion, plus the encoder's
+conserving correction; dev16.decode_bound) plus 4e-6 w_k M.
 (A bar relative to each shell's own largest value would fail where the expanded
 equilibrium of a shell passes through zero: the Bose-Einstein shell 4 does near
 z = 0.55 at theta = 1, where its populations are 1e-4 of their neighbours'.)"""
@@ -103,7 +104,7 @@ def _check_sampled(rl, params, fields, stats, precision, steps, net=None, seed=0
     sim.step(1)
     if precision == "dev16":
         f1 = torch.from_numpy(dev16.decode(rl, sim.state(), nx, ny, stats))
-        half_step = dev16.quantum(rl, sim.state(), nx, ny, stats)
+        code_bound = dev16.decode_bound(rl, sim.state(), nx, ny, stats)
     else:
         f1 = sim.populations()
     sim.close()
@@ -118,7 +119,7 @@ def _check_sampled(rl, params, fields, stats, precision, steps, net=None, seed=0
         M = np.abs(rc / v["w"]).max()
         if precision == "dev16":
             got = f1[:, y, x].double().cpu().numpy()
-            bound = half_step[:, y, x] * 1.2 + 4e-6 * v["w"] * M
+            bound = code_bound[:, y, x] + 4e-6 * v["w"] * M
         else:
             got = f1[:, y, x].double().cpu().numpy()
             bound = 4e-6 * v["w"] * M

@@ -71,8 +71,12 @@ def test_hotspot_order_deviations(rl):
     """eps_theta^(N), eps_q^(N) of orders 2-4 against order 5 at t = 100, FP64, against
     the values printed in Sec. 3.5.  Measured here: heat-flux deviations of orders 2
     and 3 within 10% of the printed ones, order 4 at 0.72 of it; temperature
-    deviations 0.8, 0.6, 0.3 of the printed ones; the same decrease with the order.
-    Bars: eps_q within 10% for N = 2, 3; every value within a factor 4; decreasing."""
+    deviations 0.79, 0.62, 0.32 of the printed ones; the same decrease with the order.
+    Other readings of the set-up move none of these by more than 2%: every order
+    started from the fifth-order equilibrium instead of its own, the disc centred at
+    255.5 with the profile averaged over rows 255 and 256, and t = 99 or 101.
+    Bars: eps_q within 10% for N = 2, 3 and 30% for N = 4; eps_theta below the
+    printed value and above a quarter of it; decreasing with the order."""
     params, fields = workloads.hotspot_paper()
     prof = {}
     for order in (2, 3, 4, 5):
@@ -89,9 +93,8 @@ def test_hotspot_order_deviations(rl):
         eq = 100 * np.abs(q - q5).sum() / np.abs(q5).sum()
         pt, pq = rows[order]
         print(f"  N={order}: eps_theta {et:.3f}% (paper {pt}%)  eps_q {eq:.3f}% (paper {pq}%)")
-        if order in (2, 3):
-            assert abs(eq / pq - 1) < 0.10, (order, eq, pq)
-        assert 0.25 < et / pt < 4 and 0.25 < eq / pq < 4, (order, et, eq)
+        assert abs(eq / pq - 1) < (0.10 if order in (2, 3) else 0.30), (order, eq, pq)
+        assert 0.25 < et / pt < 1.0, (order, et, pt)
     # the deviations fall with the order, as in the paper
     ets = [100 * np.abs(prof[o][0] - th5).sum() / th5.sum() for o in (2, 3, 4)]
     eqs = [100 * np.abs(prof[o][1] - q5).sum() / np.abs(q5).sum() for o in (2, 3, 4)]
