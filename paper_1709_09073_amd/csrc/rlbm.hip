@@ -36,6 +36,9 @@
 #ifndef RLBM_STEP_WAVES_FDBE
 #define RLBM_STEP_WAVES_FDBE 3       // FD/BE fit 3 waves without spills with the shortened FP32-path sums
 #endif
+#ifndef RLBM_FP32_STAGED
+#define RLBM_FP32_STAGED 0      // 1: FP32 populations take the staged pull too (tiles that fit)
+#endif
 #ifndef RLBM_BATCH_WAVES_MJ
 #define RLBM_BATCH_WAVES_MJ 2   // measured: 3 waves spill in the batch kernel and run ~10% slower
 #endif
@@ -894,15 +897,17 @@ __device__ __forceinline__ void pull_dev(const void *fin, long long plane, int n
     dev_pull_direction<ST, 11>(base, rs, plane, nx, x, y, xl, xr, yd, yu, f);
 }
 
-// ---------------------------------------------------------------- tile-staged pull (16-bit deviations)
+// ---------------------------------------------------------------- tile-staged pull
 // A workgroup covers a tile of tx x ty cells; its halo tile of (tx + 2) x (ty + 2) source
-// cells is decoded once per direction into LDS (six floats per cell, f/w), and every
-// cell then interpolates its direction from LDS.  Each source value is decoded about
-// 1.3 times per step (the halo) instead of up to four times (once per pulling cell).
-// Two LDS buffers alternate between directions, so one barrier per direction suffices.
-// Halo cell h (row-major in the halo tile) is decoded by thread h and, for h >= 256,
-// by thread h - 256; tiles with more than 512 halo cells use the direct pull.
-constexpr int DEV16_MAX_HALO = 512;
+// cells is read once per direction into LDS (six floats per cell; 16-bit deviations are
+// decoded on the way), and every cell then interpolates its direction from LDS.  Each
+// source value is read (and decoded) about 1.3 times per step instead of up to four
+// times (once per pulling cell).  Two LDS buffers alternate between directions, so
+// one barrier per direction suffices, and the next direction's halo values are
+// requested before that barrier.  Halo cell h (row-major in the halo tile) is handled
+// by thread h and, for h >= 256, by thread h - 256; tiles with more than 512 halo
+// cells use the direct pull.
+constexpr int STAGED_MAX_HALO = 512;
 
 // source coordinate of a halo position (one step outside the grid at most matters;
 // positions further out feed only cells outside the grid and are clamped in bounds)
@@ -912,36 +917,78 @@ __device__ __forceinline__ int halo_src(int g, int n, int bc_lo, int bc_hi) {
     return g;
 }
 
+// What the staged pull reads per halo cell and direction, and how it becomes six floats.
+template <int ST, typename S>
+struct Stage;
+
+template <int ST>
+struct Stage<ST, Dev16> {
+    using Raw = u32x3;                 // six SNORM16 codes
+    using Side = DecodeRef;            // the cell's side record, read once per step
+    static __device__ __forceinline__ void side(const void *fin, long long plane, unsigned cell, Side &d) {
+        const rsrc_t rs = make_rsrc((const char *)fin + 144LL * plane, 48u * (unsigned)plane);
+        SideRef sr;
+        load_side(rs, cell, sr);
+        d = decode_ref(sr);
+    }
+    template <int N>
+    static __device__ __forceinline__ void load(const void *fin, long long plane, unsigned cell, Raw &q) {
+        const rsrc_t r = make_rsrc((const char *)fin + (long long)N * plane * 12, 12u * (unsigned)plane);
+        q = __builtin_amdgcn_raw_buffer_load_b96(r, cell * 12u, 0u, LOAD_POLICY);
+    }
+    template <int N>
+    static __device__ __forceinline__ void value(const Side &d, const Raw &q, float (&g)[6]) { dev_decode<ST, N>(d, q, g); }
+};
+
+template <int ST>
+struct Stage<ST, float> {
+    struct Raw {
+        float v[6];
+    };
+    struct Side {};
+    static __device__ __forceinline__ void side(const void *, long long, unsigned, Side &) {}
+    template <int N>
+    static __device__ __forceinline__ void load(const void *fin, long long plane, unsigned cell, Raw &q) {
+        const rsrc_t r = make_rsrc((const float *)fin + (long long)(6 * N) * plane, 24u * (unsigned)plane);
+        Rec<float>::load(r, cell, (unsigned)plane, q.v);
+    }
+    template <int N>
+    static __device__ __forceinline__ void value(const Side &, const Raw &q, float (&g)[6]) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) g[k] = q.v[k];
+    }
+};
+
+template <int ST, typename S>
 struct HaloCell {
-    DecodeRef d;
+    typename Stage<ST, S>::Side side;
     unsigned cell;
     bool valid;
 };
 
-template <int N>
-__device__ __forceinline__ void dev_load_halo(const char *base, long long plane, const HaloCell (&hc)[2],
-                                              u32x3 (&q)[2]) {
-    const rsrc_t r = make_rsrc(base + (long long)N * plane * 12, 12u * (unsigned)plane);
+template <int ST, typename S, int N>
+__device__ __forceinline__ void stage_load(const void *fin, long long plane, const HaloCell<ST, S> (&hc)[2],
+                                           typename Stage<ST, S>::Raw (&q)[2]) {
 #pragma unroll
     for (int j = 0; j < 2; ++j)
-        q[j] = hc[j].valid ? __builtin_amdgcn_raw_buffer_load_b96(r, hc[j].cell * 12u, 0u, LOAD_POLICY) : u32x3{0u, 0u, 0u};
+        if (hc[j].valid) Stage<ST, S>::template load<N>(fin, plane, hc[j].cell, q[j]);
 }
 
-template <int ST, int N>
-__device__ __forceinline__ void dev_stage_direction(const HaloCell (&hc)[2], const u32x3 (&q)[2], int tid, float *buf) {
+template <int ST, typename S, int N>
+__device__ __forceinline__ void stage_write(const HaloCell<ST, S> (&hc)[2], const typename Stage<ST, S>::Raw (&q)[2],
+                                            int tid, float *buf) {
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
         if (!hc[j].valid) continue;
         float g[6];
-        dev_decode<ST, N>(hc[j].d, q[j], g);
+        Stage<ST, S>::template value<N>(hc[j].side, q[j], g);
         float *dst = buf + 6 * (tid + 256 * j);
 #pragma unroll
         for (int k = 0; k < 6; k += 2) *reinterpret_cast<float2 *>(dst + k) = make_float2(g[k], g[k + 1]);
     }
 }
 
-template <int N>
-__device__ __forceinline__ void dev_read_tap(const float *buf, int h, float (&g)[6]) {
+__device__ __forceinline__ void lds_read_tap(const float *buf, int h, float (&g)[6]) {
     const float *src = buf + 6 * h;
 #pragma unroll
     for (int k = 0; k < 6; k += 2) {
@@ -953,37 +1000,36 @@ __device__ __forceinline__ void dev_read_tap(const float *buf, int h, float (&g)
 
 // Direction N of the cell at halo position (hx, hy) from the staged buffer.
 template <int N>
-__device__ __forceinline__ void dev_lds_direction(const float *buf, int hw, int hx, int hy, float (&f)[72]) {
+__device__ __forceinline__ void lds_direction(const float *buf, int hw, int hx, int hy, float (&f)[72]) {
     const int xb = cdir(N) > 0.1 ? hx - 1 : (cdir(N) < -0.1 ? hx + 1 : hx);
     const int yb = sdir(N) > 0.1 ? hy - 1 : (sdir(N) < -0.1 ? hy + 1 : hy);
     if constexpr (N % 3 == 0) {
         float g[6];
-        dev_read_tap<N>(buf, yb * hw + xb, g);
+        lds_read_tap(buf, yb * hw + xb, g);
 #pragma unroll
         for (int k = 0; k < 6; ++k) f[6 * N + k] = g[k];
     } else {
         float bb[6], bx[6], cb[6], cx[6];
-        dev_read_tap<N>(buf, yb * hw + xb, bb);
-        dev_read_tap<N>(buf, yb * hw + hx, bx);
-        dev_read_tap<N>(buf, hy * hw + xb, cb);
-        dev_read_tap<N>(buf, hy * hw + hx, cx);
+        lds_read_tap(buf, yb * hw + xb, bb);
+        lds_read_tap(buf, yb * hw + hx, bx);
+        lds_read_tap(buf, hy * hw + xb, cb);
+        lds_read_tap(buf, hy * hw + hx, cx);
         dev_interp<N>(bb, bx, cb, cx, f);
     }
 }
 
-// One direction of the staged pull.  The halo's packed deviations of direction N
-// arrived in q during the previous round; direction N + 1's are requested first, so
-// their latency overlaps this round's decode, barrier and interpolation.
-template <int ST, int N>
-__device__ __forceinline__ void dev_tile_round(const char *base, long long plane, const HaloCell (&hc)[2], int tid,
-                                               float *lds, int nh, int hw, int hx, int hy, bool use, u32x3 (&q)[2],
-                                               float (&f)[72]) {
-    u32x3 qn[2];
-    if constexpr (N < 11) dev_load_halo<N + 1>(base, plane, hc, qn);
+// One direction of the staged pull: q holds direction N's halo values (requested in
+// the previous round); direction N + 1's are requested first.
+template <int ST, typename S, int N>
+__device__ __forceinline__ void stage_round(const void *fin, long long plane, const HaloCell<ST, S> (&hc)[2], int tid,
+                                            float *lds, int nh, int hw, int hx, int hy, bool use,
+                                            typename Stage<ST, S>::Raw (&q)[2], float (&f)[72]) {
+    typename Stage<ST, S>::Raw qn[2];
+    if constexpr (N < 11) stage_load<ST, S, N + 1>(fin, plane, hc, qn);
     float *buf = lds + (N & 1) * 6 * nh;
-    dev_stage_direction<ST, N>(hc, q, tid, buf);
+    stage_write<ST, S, N>(hc, q, tid, buf);
     __syncthreads();
-    if (use) dev_lds_direction<N>(buf, hw, hx, hy, f);
+    if (use) lds_direction<N>(buf, hw, hx, hy, f);
     if constexpr (N < 11) {
         q[0] = qn[0];
         q[1] = qn[1];
@@ -994,14 +1040,12 @@ __device__ __forceinline__ void dev_tile_round(const char *base, long long plane
 // workgroup calls it (it holds barriers); `use` says whether this thread's own pull
 // position (hx, hy) (halo coordinates, its stencil inside the halo tile) takes the
 // staged values.
-template <int ST>
-__device__ __forceinline__ void dev_tile_pull(const KArgs &a, int x0, int y0, float *lds, int hx, int hy, bool use,
-                                              float (&f)[72]) {
-    const char *base = (const char *)a.fin;
+template <int ST, typename S>
+__device__ __forceinline__ void staged_pull(const KArgs &a, int x0, int y0, float *lds, int hx, int hy, bool use,
+                                            float (&f)[72]) {
     const int tid = (int)threadIdx.x;
     const int hw = a.tx + 2, nh = hw * (a.ty + 2);
-    const rsrc_t rs = make_rsrc(base + 144LL * a.plane, 48u * (unsigned)a.plane);
-    HaloCell hc[2];
+    HaloCell<ST, S> hc[2];
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
         const int h = tid + 256 * j;
@@ -1010,26 +1054,22 @@ __device__ __forceinline__ void dev_tile_pull(const KArgs &a, int x0, int y0, fl
         const int sx = halo_src(x0 - 1 + hxx, a.nx, a.bc_xlo, a.bc_xhi);
         const int sy = halo_src(y0 - 1 + hyy, a.ny, a.bc_ylo, a.bc_yhi);
         hc[j].cell = hc[j].valid ? (unsigned)(sy * a.nx + sx) : 0u;
-        if (hc[j].valid) {
-            SideRef sr;
-            load_side(rs, hc[j].cell, sr);
-            hc[j].d = decode_ref(sr);
-        }
+        if (hc[j].valid) Stage<ST, S>::side(a.fin, a.plane, hc[j].cell, hc[j].side);
     }
-    u32x3 q[2];
-    dev_load_halo<0>(base, a.plane, hc, q);
-    dev_tile_round<ST, 0>(base, a.plane, hc, tid, lds, nh, hw, hx, hy, use, q, f);
-    dev_tile_round<ST, 1>(base, a.plane, hc, tid, lds, nh, hw, hx, hy, use, q, f);
-    dev_tile_round<ST, 2>(base, a.plane, hc, tid, lds, nh, hw, hx, hy, use, q, f);
-    dev_tile_round<ST, 3>(base, a.plane, hc, tid, lds, nh, hw, hx, hy, use, q, f);
-    dev_tile_round<ST, 4>(base, a.plane, hc, tid, lds, nh, hw, hx, hy, use, q, f);
-    dev_tile_round<ST, 5>(base, a.plane, hc, tid, lds, nh, hw, hx, hy, use, q, f);
-    dev_tile_round<ST, 6>(base, a.plane, hc, tid, lds, nh, hw, hx, hy, use, q, f);
-    dev_tile_round<ST, 7>(base, a.plane, hc, tid, lds, nh, hw, hx, hy, use, q, f);
-    dev_tile_round<ST, 8>(base, a.plane, hc, tid, lds, nh, hw, hx, hy, use, q, f);
-    dev_tile_round<ST, 9>(base, a.plane, hc, tid, lds, nh, hw, hx, hy, use, q, f);
-    dev_tile_round<ST, 10>(base, a.plane, hc, tid, lds, nh, hw, hx, hy, use, q, f);
-    dev_tile_round<ST, 11>(base, a.plane, hc, tid, lds, nh, hw, hx, hy, use, q, f);
+    typename Stage<ST, S>::Raw q[2];
+    stage_load<ST, S, 0>(a.fin, a.plane, hc, q);
+    stage_round<ST, S, 0>(a.fin, a.plane, hc, tid, lds, nh, hw, hx, hy, use, q, f);
+    stage_round<ST, S, 1>(a.fin, a.plane, hc, tid, lds, nh, hw, hx, hy, use, q, f);
+    stage_round<ST, S, 2>(a.fin, a.plane, hc, tid, lds, nh, hw, hx, hy, use, q, f);
+    stage_round<ST, S, 3>(a.fin, a.plane, hc, tid, lds, nh, hw, hx, hy, use, q, f);
+    stage_round<ST, S, 4>(a.fin, a.plane, hc, tid, lds, nh, hw, hx, hy, use, q, f);
+    stage_round<ST, S, 5>(a.fin, a.plane, hc, tid, lds, nh, hw, hx, hy, use, q, f);
+    stage_round<ST, S, 6>(a.fin, a.plane, hc, tid, lds, nh, hw, hx, hy, use, q, f);
+    stage_round<ST, S, 7>(a.fin, a.plane, hc, tid, lds, nh, hw, hx, hy, use, q, f);
+    stage_round<ST, S, 8>(a.fin, a.plane, hc, tid, lds, nh, hw, hx, hy, use, q, f);
+    stage_round<ST, S, 9>(a.fin, a.plane, hc, tid, lds, nh, hw, hx, hy, use, q, f);
+    stage_round<ST, S, 10>(a.fin, a.plane, hc, tid, lds, nh, hw, hx, hy, use, q, f);
+    stage_round<ST, S, 11>(a.fin, a.plane, hc, tid, lds, nh, hw, hx, hy, use, q, f);
 }
 
 // Shell scale kept as an IEEE half no smaller than s: s (1 + 2^-10) + 2^-24 rounds to
@@ -1298,12 +1338,12 @@ __device__ __forceinline__ void step_cell(const KArgs &a, int x, int y) {
     finish_cell<ST, S, R, N, FORCED>(a, x, y, c, f);
 }
 
-// One tile of 16-bit deviation populations with the staged pull.  All threads of the
-// workgroup take part in the staging (its barriers); cells outside the grid stop after
-// it.  A wall cell whose fluid neighbour's stencil falls outside the halo tile (the
-// high x wall when a tile starts on it) pulls directly, with the same arithmetic.
-template <int ST>
-__device__ __forceinline__ void dev16_tile(const KArgs &a, int txi, int tyi, float *lds) {
+// One tile with the staged pull (16-bit deviations or FP32 populations).  All threads
+// of the workgroup take part in the staging (its barriers); cells outside the grid stop
+// after it.  A wall cell whose fluid neighbour's stencil falls outside the halo tile
+// (the high x wall when a tile starts on it) pulls directly, with the same arithmetic.
+template <int ST, typename S>
+__device__ __forceinline__ void staged_tile(const KArgs &a, int txi, int tyi, float *lds) {
     const int x0 = txi * a.tx, y0 = tyi * a.ty;
     const int lx = (int)threadIdx.x % a.tx, ly = (int)threadIdx.x / a.tx;
     const int x = x0 + lx, y = y0 + ly;
@@ -1312,10 +1352,10 @@ __device__ __forceinline__ void dev16_tile(const KArgs &a, int txi, int tyi, flo
     const int hx = c.xe - x0 + 1, hy = c.ye - y0 + 1;
     const bool inside = hx >= 1 && hx <= a.tx && hy >= 1 && hy <= a.ty;
     float f[72];
-    dev_tile_pull<ST>(a, x0, y0, lds, hx, hy, active && inside, f);
+    staged_pull<ST, S>(a, x0, y0, lds, hx, hy, active && inside, f);
     if (!active) return;
-    if (!inside) pull_cell<Dev16, float, ST>(a, c, f);
-    finish_cell<ST, Dev16, float, 5, false>(a, x, y, c, f);
+    if (!inside) pull_cell<S, float, ST>(a, c, f);
+    finish_cell<ST, S, float, 5, false>(a, x, y, c, f);
 }
 
 template <int ST, typename S, typename R, int N = 5, bool FORCED = false>
@@ -1325,16 +1365,16 @@ __global__ RLBM_STEP_BOUNDS(ST, R, FORCED) void k_step(KArgs a) {
     step_cell<ST, S, R, N, FORCED>(a, x, y);
 }
 
-// Staged-pull step of 16-bit deviation populations (tiles with at most
-// DEV16_MAX_HALO halo cells); dynamic LDS: 2 x 6 floats per halo cell.
-template <int ST>
-__global__ RLBM_STEP_BOUNDS(ST, float, false) void k_step_dev16(KArgs a) {
-    extern __shared__ float dev16_lds[];
+// Staged-pull step (tiles with at most STAGED_MAX_HALO halo cells); dynamic LDS:
+// 2 x 6 floats per halo cell.
+template <int ST, typename S>
+__global__ RLBM_STEP_BOUNDS(ST, float, false) void k_step_staged(KArgs a) {
+    extern __shared__ float stage_lds[];
     const int b = blockIdx.x;
     const int t = (b & 7) * a.per_xcd + (b >> 3);
     if (t >= a.ntiles) return;                 // the whole workgroup leaves together
     const int tyi = t / a.ntx;
-    dev16_tile<ST>(a, t - tyi * a.ntx, tyi, dev16_lds);
+    staged_tile<ST, S>(a, t - tyi * a.ntx, tyi, stage_lds);
 }
 
 // Many grids in one launch.  The tiles of all grids are numbered consecutively
@@ -1346,7 +1386,7 @@ struct Batch {
     int ntiles;
     int per_xcd;        // ceil(ntiles / 8)
     int groups_per_xcd; // workgroups launched per XCD
-    int staged;         // 16-bit deviations: staged pull (dynamic LDS sized for the tile)
+    int staged;         // staged pull (dynamic LDS sized for the tile)
 };
 
 template <int ST, typename S, typename R>
@@ -1364,13 +1404,13 @@ __global__ RLBM_BATCH_BOUNDS(ST, R) void k_step_batch(Batch b, const KArgs *__re
         const int lt = t - __builtin_amdgcn_readfirstlane(tile_base[g]);
         const int tyi = lt / a.ntx;
         const int txi = lt - tyi * a.ntx;
-        if constexpr (std::is_same<S, Dev16>::value) {
+        if constexpr (!std::is_same<S, double>::value) {
             if (b.staged) {
-                extern __shared__ float dev16_lds[];
+                extern __shared__ float stage_lds[];
                 // no barrier between tiles: the buffers keep alternating by direction
                 // parity, so every read of a buffer ends before the next tile's
                 // barrier that precedes its rewrite
-                dev16_tile<ST>(a, txi, tyi, dev16_lds);
+                staged_tile<ST, S>(a, txi, tyi, stage_lds);
                 continue;
             }
         }
@@ -1394,10 +1434,10 @@ __global__ RLBM_STEP_BOUNDS(ST, R, false) void k_step_tiles(Batch b, const KArgs
     const int lt = t - __builtin_amdgcn_readfirstlane(tile_base[g]);
     const int tyi = lt / a.ntx;
     const int txi = lt - tyi * a.ntx;
-    if constexpr (std::is_same<S, Dev16>::value) {
+    if constexpr (!std::is_same<S, double>::value) {
         if (b.staged) {
-            extern __shared__ float dev16_lds[];
-            dev16_tile<ST>(a, txi, tyi, dev16_lds);
+            extern __shared__ float stage_lds[];
+            staged_tile<ST, S>(a, txi, tyi, stage_lds);
             return;
         }
     }
@@ -1533,7 +1573,7 @@ struct Kern {
         return prec == RLBM_FP64 ? k_step<ST, double, double>
              : prec == RLBM_FP32 ? k_step<ST, float, float> : k_step<ST, Dev16, float>;
     }
-    static KFn staged() { return k_step_dev16<ST>; }
+    static KFn staged(int prec) { return prec == RLBM_FP32 ? k_step_staged<ST, float> : k_step_staged<ST, Dev16>; }
     static BFn batch(int prec) {
         return prec == RLBM_FP64 ? k_step_batch<ST, double, double>
              : prec == RLBM_FP32 ? k_step_batch<ST, float, float> : k_step_batch<ST, Dev16, float>;
@@ -1593,15 +1633,17 @@ KFn pick_noneq(int st, int prec, int order) {
          : order == 4 ? noneq_kernel<RLBM_MJ, 4>(prec) : noneq_kernel<RLBM_MJ, 5>(prec);
 }
 
-KFn pick_staged(int st) {
-    return st == RLBM_MJ ? Kern<RLBM_MJ>::staged() : st == RLBM_FD ? Kern<RLBM_FD>::staged() : Kern<RLBM_BE>::staged();
+KFn pick_staged(int st, int prec) {
+    return st == RLBM_MJ ? Kern<RLBM_MJ>::staged(prec) : st == RLBM_FD ? Kern<RLBM_FD>::staged(prec)
+                                                        : Kern<RLBM_BE>::staged(prec);
 }
 
-// dynamic LDS of the staged 16-bit deviation pull for tiles of tx x ty, 0 if the
-// tile's halo is too large for it (those tiles pull directly)
+// dynamic LDS of the staged pull for tiles of tx x ty, 0 where the direct pull runs:
+// FP64 populations, and tiles whose halo exceeds STAGED_MAX_HALO cells
 size_t staged_lds_bytes(int prec, int tx, int ty) {
     const int nh = (tx + 2) * (ty + 2);
-    if (prec != RLBM_DEV16 || nh > DEV16_MAX_HALO) return 0;
+    const bool staged = prec == RLBM_DEV16 || (prec == RLBM_FP32 && RLBM_FP32_STAGED);
+    if (!staged || nh > STAGED_MAX_HALO) return 0;
     return sizeof(float) * 12 * (size_t)nh;
 }
 
@@ -1826,10 +1868,11 @@ int launch_step(rlbm_ctx *c, hipStream_t s) {
         KArgs a = c->base[0];
         a.fin = c->cur ? p0.f_b : p0.f_a;
         a.fout = c->cur ? p0.f_a : p0.f_b;
-        const size_t lds = staged_lds_bytes(p0.precision, c->tx, c->ty);
+        // the staged pull covers order 5 without forcing (16-bit deviations are
+        // only that, checked at create)
+        const size_t lds = (is_forced(p0) || p0.order != 5) ? 0 : staged_lds_bytes(p0.precision, c->tx, c->ty);
         if (lds > 0) {
-            // 16-bit deviations are order 5 without forcing (checked at create)
-            hipLaunchKernelGGL(pick_staged(p0.stats), dim3(8 * a.per_xcd), dim3(256), lds, s, a);
+            hipLaunchKernelGGL(pick_staged(p0.stats, p0.precision), dim3(8 * a.per_xcd), dim3(256), lds, s, a);
         } else {
             const KFn k = is_forced(p0) ? pick_forced(p0.stats, p0.precision) : pick_order(0, p0.stats, p0.precision, p0.order);
             hipLaunchKernelGGL(k, dim3(8 * a.per_xcd), dim3(256), 0, s, a);
