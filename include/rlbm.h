@@ -70,7 +70,11 @@ enum rlbm_stats { RLBM_MJ = 0, RLBM_FD = 1, RLBM_BE = 2 };         /* Eqs. mj-w-
  * s_k >= max_n |f_{k,n} / w_k - R_{k,n}| (an IEEE half, rounded up).  A buffer holds 12
  * direction blocks, each nx*ny cells (y-major, x fastest) of 6 SNORM16 (shells k = 0..5,
  * 12 bytes), then nx*ny cells of 48 bytes: floats rho_0..rho_5, alpha, beta, halves
- * s_0..s_5, 4 bytes of padding: 192 bytes per cell.  Arithmetic as RLBM_FP32. */
+ * s_0..s_5, 4 bytes of padding: 192 bytes per cell.  Decoding is f_i = w_k (R_i +
+ * s_k q_i / 32767).  The codes are taken against the least-squares rho, alpha, beta; the
+ * stored rho_k, alpha, beta are then corrected so that the decoded populations keep
+ * the cell's shell sums and momentum density T^{0x}, T^{0y} (Sec. 2.4 moments) to
+ * rounding.  Arithmetic as RLBM_FP32. */
 enum rlbm_precision { RLBM_FP64 = 0, RLBM_FP32 = 1, RLBM_DEV16 = 2 };
 enum rlbm_tau_mode { RLBM_TAU_CONST = 0, RLBM_TAU_INV_THETA = 1 };  /* tau, or tau_a/theta + tau_b */
 enum rlbm_bc {

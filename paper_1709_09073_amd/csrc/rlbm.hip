@@ -37,7 +37,7 @@
 #define RLBM_STEP_WAVES_FDBE 3       // FD/BE fit 3 waves without spills with the shortened FP32-path sums
 #endif
 #ifndef RLBM_FP32_STAGED
-#define RLBM_FP32_STAGED 0      // 1: FP32 populations take the staged pull too (tiles that fit)
+#define RLBM_FP32_STAGED 1      // FP32 populations take the staged pull too (tiles that fit)
 #endif
 #ifndef RLBM_BATCH_WAVES_MJ
 #define RLBM_BATCH_WAVES_MJ 2   // measured: 3 waves spill in the batch kernel and run ~10% slower
@@ -327,12 +327,42 @@ __device__ __forceinline__ Mom moments(const R (&f)[72]) {
     return m;
 }
 
+// 1/x from the hardware reciprocal estimate refined by two Newton-Raphson steps
+// (each squares the relative error): a short dependency chain without the scaling
+// steps of a correctly rounded division, for a positive normal x.
+__device__ __forceinline__ double rcp_refined(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(fma(-x, r, 1.0), r, r);
+    return fma(fma(-x, r, 1.0), r, r);
+}
+
+// a / b and 1/sqrt(x) for the FP32 and 16-bit population paths (LOOSE): the hardware
+// estimates refined by two Newton-Raphson steps, a few ulp of FP64 and far below those
+// populations' own rounding, in about half the instructions of the correctly rounded
+// forms, which FP64 populations keep.
+template <bool LOOSE>
+__device__ __forceinline__ double qdiv(double a, double b) {
+    if constexpr (LOOSE) return a * rcp_refined(b);
+    else return a / b;
+}
+template <bool LOOSE>
+__device__ __forceinline__ double inv_sqrt(double x) {
+    if constexpr (LOOSE) {
+        double r = __builtin_amdgcn_rsq(x);
+        r = r * fma(-0.5 * x * r, r, 1.5);
+        return r * fma(-0.5 * x * r, r, 1.5);
+    } else {
+        return 1.0 / sqrt(x);
+    }
+}
+
 // ---------------------------------------------------------------- Landau frame
+template <bool LOOSE>
 __device__ __forceinline__ void landau(const Mom &m, double &ux, double &uy, double &eps, unsigned &flags) {
-    const double inv = 1.0 / m.T00;
+    const double inv = qdiv<LOOSE>(1.0, m.T00);
     const double mx = m.T01 * inv, my = m.T02 * inv;
     const double M2 = mx * mx + my * my;
-    const double sc = 4.0 / (3.0 + sqrt(fmax(9.0 - 8.0 * M2, 0.0)));
+    const double sc = qdiv<LOOSE>(4.0, 3.0 + sqrt(fmax(9.0 - 8.0 * M2, 0.0)));
     ux = sc * mx;
     uy = sc * my;
     bool conv = false;
@@ -342,7 +372,7 @@ __device__ __forceinline__ void landau(const Mom &m, double &ux, double &uy, dou
         const double Fy = m.T02 - m.T12 * ux - m.T22 * uy - e * uy;
         const double a = -m.T11 + m.T01 * ux - e, b = -m.T12 + m.T02 * ux;
         const double c = -m.T12 + m.T01 * uy, d = -m.T22 + m.T02 * uy - e;
-        const double idet = 1.0 / (a * d - b * c);
+        const double idet = qdiv<LOOSE>(1.0, a * d - b * c);
         const double dx = (d * Fx - b * Fy) * idet, dy = (a * Fy - c * Fx) * idet;
         ux -= dx;
         uy -= dy;
@@ -450,15 +480,6 @@ __device__ __forceinline__ void gvals(double mu, double (&g)[7], unsigned &flags
     }
 }
 
-// 1/x from the hardware reciprocal estimate refined by two Newton-Raphson steps
-// (each squares the relative error): a short dependency chain without the scaling
-// steps of a correctly rounded division, for a positive normal x.
-__device__ __forceinline__ double rcp_refined(double x) {
-    double r = __builtin_amdgcn_rcp(x);
-    r = fma(fma(-x, r, 1.0), r, r);
-    return fma(fma(-x, r, 1.0), r, r);
-}
-
 // Newton on mu = ln z leaves an error C dmu^2 after a step dmu, with C = f''/(2 f')
 // at most 0.5 for FD and about 0.5/|mu| for BE near mu = 0, so a step below this
 // tolerance is applied and ends the solve (no confirming evaluation).  FP64
@@ -562,13 +583,13 @@ struct Macro {
 template <int ST, bool LOOSE>
 __device__ __forceinline__ void state_from_moments(const Mom &m, Macro &M, unsigned &flags, const KArgs &a,
                                                    int &iters, double *L_out = nullptr) {
-    landau(m, M.ux, M.uy, M.eps, flags);
+    landau<LOOSE>(m, M.ux, M.uy, M.eps, flags);
     const double u2 = M.ux * M.ux + M.uy * M.uy;
     if (!(u2 < 1.0)) {
         flags |= RLBM_FLAG_SUPERLUMINAL;
         M.ux = M.uy = 0.0;
     }
-    M.ga = 1.0 / sqrt(1.0 - (M.ux * M.ux + M.uy * M.uy));
+    M.ga = inv_sqrt<LOOSE>(1.0 - (M.ux * M.ux + M.uy * M.uy));
     M.n = M.ga * (m.N0 - M.ux * m.Nx - M.uy * m.Ny);
     // a NaN or infinite population makes N^0 and T^00 (every p^0 > 0) and so n or eps
     // non-finite; comparisons with NaN are false
@@ -577,11 +598,11 @@ __device__ __forceinline__ void state_from_moments(const Mom &m, Macro &M, unsig
         M.n = (M.n > 0.0 && M.n < INFINITY) ? M.n : 1.0;
         M.eps = (M.eps > 0.0 && M.eps < INFINITY) ? M.eps : 1.0;
     }
-    const double r = 2.0 * M.n * M.n * M.n / (PI_D * M.eps * M.eps);
+    const double r = qdiv<LOOSE>(2.0 * M.n * M.n * M.n, PI_D * M.eps * M.eps);
     if (L_out) *L_out = log(r);
     iters = 0;
     if constexpr (ST == RLBM_MJ) {
-        M.theta = M.eps / (2.0 * M.n);
+        M.theta = qdiv<LOOSE>(M.eps, 2.0 * M.n);
         M.z = r;
 #pragma unroll
         for (int k = 1; k <= 6; ++k) M.g[k] = r;
@@ -592,7 +613,8 @@ __device__ __forceinline__ void state_from_moments(const Mom &m, Macro &M, unsig
         const double mu = invert_h<ST, LOOSE>(r, mu0, flags, iters);
         gvals<ST, 1, 6, LOOSE>(mu, M.g, flags);
         M.z = exp(mu);
-        M.theta = 0.5 * (M.g[2] / M.g[3]) * (M.eps / M.n);
+        if constexpr (LOOSE) M.theta = qdiv<LOOSE>(0.5 * M.g[2] * M.eps, M.g[3] * M.n);
+        else M.theta = 0.5 * (M.g[2] / M.g[3]) * (M.eps / M.n);
     }
 }
 
@@ -693,7 +715,7 @@ __device__ __forceinline__ void equilibrium_relax(const Macro &M, double tau, R 
     }
     R om[12];
     if constexpr (COLLIDE) {
-        const R gt = (R)(M.ga / tau);
+        const R gt = (R)qdiv<sizeof(R) == 4>(M.ga, tau);
         const R ux = (R)M.ux, uy = (R)M.uy;
 #pragma unroll
         for (int n = 0; n < 6; ++n) {
@@ -903,8 +925,8 @@ __device__ __forceinline__ void pull_dev(const void *fin, long long plane, int n
 // decoded on the way), and every cell then interpolates its direction from LDS.  Each
 // source value is read (and decoded) about 1.3 times per step instead of up to four
 // times (once per pulling cell).  Two LDS buffers alternate between directions, so
-// one barrier per direction suffices, and the next direction's halo values are
-// requested before that barrier.  Halo cell h (row-major in the halo tile) is handled
+// one barrier per direction suffices, and the halo values of the next STAGE_AHEAD
+// directions are in flight during each round.  Halo cell h (row-major in the halo tile) is handled
 // by thread h and, for h >= 256, by thread h - 256; tiles with more than 512 halo
 // cells use the direct pull.
 constexpr int STAGED_MAX_HALO = 512;
@@ -966,12 +988,15 @@ struct HaloCell {
     bool valid;
 };
 
+// Loads are issued for both halo slots whether or not the slot holds a halo cell (an
+// empty slot reads cell 0 and is never written to LDS): with no branch around them the
+// compiler can wait for exactly the previous direction's loads and leave the next
+// direction's in flight.
 template <int ST, typename S, int N>
 __device__ __forceinline__ void stage_load(const void *fin, long long plane, const HaloCell<ST, S> (&hc)[2],
                                            typename Stage<ST, S>::Raw (&q)[2]) {
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
-        if (hc[j].valid) Stage<ST, S>::template load<N>(fin, plane, hc[j].cell, q[j]);
+    for (int j = 0; j < 2; ++j) Stage<ST, S>::template load<N>(fin, plane, hc[j].cell, q[j]);
 }
 
 template <int ST, typename S, int N>
@@ -1018,21 +1043,39 @@ __device__ __forceinline__ void lds_direction(const float *buf, int hw, int hx, 
     }
 }
 
-// One direction of the staged pull: q holds direction N's halo values (requested in
-// the previous round); direction N + 1's are requested first.
+// Directions whose halo values are in flight while a round works (register cost:
+// STAGE_AHEAD x 2 halo slots x 3 (16-bit deviations) or 6 (FP32) registers).
+#ifndef RLBM_STAGE_AHEAD
+#define RLBM_STAGE_AHEAD 2
+#endif
+constexpr int STAGE_AHEAD = RLBM_STAGE_AHEAD;
+
+// One direction of the staged pull: q[i] holds direction N + i's halo values (requested
+// in earlier rounds); direction N + STAGE_AHEAD's are requested first.
 template <int ST, typename S, int N>
 __device__ __forceinline__ void stage_round(const void *fin, long long plane, const HaloCell<ST, S> (&hc)[2], int tid,
                                             float *lds, int nh, int hw, int hx, int hy, bool use,
-                                            typename Stage<ST, S>::Raw (&q)[2], float (&f)[72]) {
+                                            typename Stage<ST, S>::Raw (&q)[STAGE_AHEAD][2], float (&f)[72]) {
     typename Stage<ST, S>::Raw qn[2];
-    if constexpr (N < 11) stage_load<ST, S, N + 1>(fin, plane, hc, qn);
+    if constexpr (N + STAGE_AHEAD < 12) stage_load<ST, S, N + STAGE_AHEAD>(fin, plane, hc, qn);
     float *buf = lds + (N & 1) * 6 * nh;
-    stage_write<ST, S, N>(hc, q, tid, buf);
+    stage_write<ST, S, N>(hc, q[0], tid, buf);
     __syncthreads();
     if (use) lds_direction<N>(buf, hw, hx, hy, f);
-    if constexpr (N < 11) {
-        q[0] = qn[0];
-        q[1] = qn[1];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+#pragma unroll
+        for (int i = 0; i + 1 < STAGE_AHEAD; ++i) q[i][j] = q[i + 1][j];
+        if constexpr (N + STAGE_AHEAD < 12) q[STAGE_AHEAD - 1][j] = qn[j];
+    }
+}
+
+template <int ST, typename S, int I>
+__device__ __forceinline__ void stage_prime(const void *fin, long long plane, const HaloCell<ST, S> (&hc)[2],
+                                            typename Stage<ST, S>::Raw (&q)[STAGE_AHEAD][2]) {
+    if constexpr (I < STAGE_AHEAD) {
+        stage_load<ST, S, I>(fin, plane, hc, q[I]);
+        stage_prime<ST, S, I + 1>(fin, plane, hc, q);
     }
 }
 
@@ -1054,10 +1097,10 @@ __device__ __forceinline__ void staged_pull(const KArgs &a, int x0, int y0, floa
         const int sx = halo_src(x0 - 1 + hxx, a.nx, a.bc_xlo, a.bc_xhi);
         const int sy = halo_src(y0 - 1 + hyy, a.ny, a.bc_ylo, a.bc_yhi);
         hc[j].cell = hc[j].valid ? (unsigned)(sy * a.nx + sx) : 0u;
-        if (hc[j].valid) Stage<ST, S>::side(a.fin, a.plane, hc[j].cell, hc[j].side);
+        Stage<ST, S>::side(a.fin, a.plane, hc[j].cell, hc[j].side);
     }
-    typename Stage<ST, S>::Raw q[2];
-    stage_load<ST, S, 0>(a.fin, a.plane, hc, q);
+    typename Stage<ST, S>::Raw q[STAGE_AHEAD][2];
+    stage_prime<ST, S, 0>(a.fin, a.plane, hc, q);
     stage_round<ST, S, 0>(a.fin, a.plane, hc, tid, lds, nh, hw, hx, hy, use, q, f);
     stage_round<ST, S, 1>(a.fin, a.plane, hc, tid, lds, nh, hw, hx, hy, use, q, f);
     stage_round<ST, S, 2>(a.fin, a.plane, hc, tid, lds, nh, hw, hx, hy, use, q, f);
@@ -1301,7 +1344,7 @@ __device__ __forceinline__ void finish_cell(const KArgs &a, int x, int y, const 
         state_from_n_theta<ST>(n, wall_lo ? a.th_wall_lo : a.th_wall_hi, M, flags);
         equilibrium_relax<ST, EQ_SET, R, N, std::is_same<S, Dev16>::value>(M, 1.0, f);
     } else {
-        const double tau = (a.tau_mode == RLBM_TAU_CONST) ? a.tau : a.tau_a / M.theta + a.tau_b;
+        const double tau = (a.tau_mode == RLBM_TAU_CONST) ? a.tau : qdiv<sizeof(R) == 4>(a.tau_a, M.theta) + a.tau_b;
         if constexpr (FORCED) {
             // momentum update: the collision sees u + a tau
             M.ux += a.force_x * tau;
