@@ -82,16 +82,33 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def recorded_traffic(workload, precision):
+def step_kernel(params, precision, order, tile, batch):
+    """Name of the step kernel a launch runs: the staged pull for FP32 and 16-bit
+    populations at order 5 without forcing on tiles whose halo has at most 512 cells,
+    the direct pull otherwise; batches run the one-tile-per-workgroup kernel."""
+    st = {"MJ": 0, "FD": 1, "BE": 2}[params.get("stats", "MJ")]
+    forced = any(params.get("force", (0.0, 0.0))) or "wall_neq" in tuple(params.get("bc", ()))
+    tx, ty = tile
+    staged = precision in ("fp32", "dev16") and order == 5 and not forced and (tx + 2) * (ty + 2) <= 512
+    S = {"fp64": "double", "fp32": "float", "dev16": "Dev16"}[precision]
+    R = "double" if precision == "fp64" else "float"
+    if batch:
+        return f"k_step_tiles<{st}, {S}, {R}> ({'staged' if staged else 'direct'} pull)"
+    if staged:
+        return f"k_step_staged<{st}, {S}>"
+    return f"k_step<{st}, {S}, {R}, {order}, {'true' if forced else 'false'}>"
+
+
+def recorded_traffic(workload, precision, tile):
     """HBM bytes per launch from the committed rocprofv3 counter runs, if they were taken
-    on the current kernel source; else None."""
+    on the current kernel source and the same tile shape; else None."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
     try:
         with open(path) as fh:
             rec = json.load(fh).get(f"{workload}/{precision}")
     except (OSError, ValueError):
         return None
-    if not rec or rec.get("source_sha256") != kernel_source_hash():
+    if not rec or rec.get("source_sha256") != kernel_source_hash() or rec.get("tile") != f"{tile[0]}x{tile[1]}":
         return None
     return rec["traffic_bytes_per_launch"]
 
@@ -241,9 +258,11 @@ def error_vs_fp64(name, net):
             params.update(guess="mlp", mlp=net.w)
         sim = rlbm.Sim(params, fields)
         del fields
-        for done in range(0, steps, 1000):
-            sim.step(min(1000, steps - done))
+        for done in range(0, steps, 500):
+            sim.step(min(500, steps - done))
             sim.sync()
+            print(f"[bench]   {prec} ({guess} guess): {min(done + 500, steps)}/{steps} steps", file=sys.stderr,
+                  flush=True)
         out = sim.fields()
         sim.close()
         torch.cuda.synchronize()
@@ -354,6 +373,9 @@ def main():
     bytes_per_launch = 2 * cell_bytes * ncell
     launch_s = ms * 1e-3 / args.steps
     achieved = bytes_per_launch / launch_s / 1e9
+    tile_used = tuple(int(v) for v in args.tile.split()[0].split("x"))
+    batch = "grids" in params
+    kernel = step_kernel(dict(stats="MJ") if batch else params, args.precision, args.order, tile_used, batch)
     diag = time_diagnostics(sim, ncell, cell_bytes) if args.diagnostics and "grids" not in params else None
     sim.close()
     print(f"[bench] {mlups:.1f} MLUPS, {achieved:.0f} GB/s, status=0x{status:x}", file=sys.stderr, flush=True)
@@ -378,8 +400,8 @@ def main():
                    "status_bits": status},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": recorded_traffic(args.workload, args.precision),
-                     "algorithmic_bytes_per_launch": bytes_per_launch, "kernel": "k_step"},
+                     "traffic": recorded_traffic(args.workload, args.precision, tile_used),
+                     "algorithmic_bytes_per_launch": bytes_per_launch, "kernel": kernel},
     }
     if diag is not None:
         out["diagnostics"] = diag
