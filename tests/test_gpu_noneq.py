@@ -5,7 +5,7 @@ Bars are relative to the per-cell scale sum_i |f_i| |p_i^x|^r, the size of the t
 sums whose difference pi is.  FP64 populations: 2e-13 for every rank after 6 steps
 (each sum carries ~1e-15 relative rounding per step on either side; the errors seen
 stay below 2.5e-14).  FP32 populations: 2e-6 for every rank (storage rounding 2^-24
-per step plus the FP32 equilibrium synthesis; seen: below 5e-7).  FP16 deviations:
+per step plus the FP32 equilibrium synthesis; seen: below 5e-7).  16-bit deviations:
 the same bar against the oracle run on the decoded GPU state."""
 import numpy as np
 import pytest
