@@ -176,11 +176,15 @@ int rlbm_step(rlbm_ctx *ctx, int64_t nsteps);
  * (Project extension: scheduling of the update of Sec. 2.1, not part of the method.) */
 int rlbm_capture(rlbm_ctx *ctx);
 
-/* (Project extension; scheduling only, results do not depend on it.)
+/* (Project extension; scheduling only, results do not depend on it: every shape and
+ * mode gives the same bits.)
  * Set the workgroup tile (tile_x * tile_y = 256, tile_x a power of two >= 16) and,
  * for a batch, the launch mode: persistent > 0 launches that many workgroups per
  * XCD, each sweeping tiles of its XCD's range; 0 launches one workgroup per tile.
- * Drops captured graphs.  Errors: RLBM_EINVAL, RLBM_EHIP. */
+ * The tile also selects the pull of FP32 and 16-bit populations at order 5 without
+ * forcing: tiles whose (tile_x + 2)(tile_y + 2) halo has at most 512 cells (32x8, 64x4,
+ * 16x16) read each direction's halo once into LDS, the others (128x2, 256x1) read the
+ * taps directly.  Drops captured graphs.  Errors: RLBM_EINVAL, RLBM_EHIP. */
 int rlbm_configure(rlbm_ctx *ctx, int32_t tile_x, int32_t tile_y, int32_t persistent);
 
 /* (Project extension; scheduling only.)
