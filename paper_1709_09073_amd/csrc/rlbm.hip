@@ -923,12 +923,13 @@ __device__ __forceinline__ void pull_dev(const void *fin, long long plane, int n
 // A workgroup covers a tile of tx x ty cells; its halo tile of (tx + 2) x (ty + 2) source
 // cells is read once per direction into LDS (six floats per cell; 16-bit deviations are
 // decoded on the way), and every cell then interpolates its direction from LDS.  Each
-// source value is read (and decoded) about 1.3 times per step instead of up to four
-// times (once per pulling cell).  Two LDS buffers alternate between directions, so
-// one barrier per direction suffices, and the halo values of the next STAGE_AHEAD
-// directions are in flight during each round.  Halo cell h (row-major in the halo tile) is handled
-// by thread h and, for h >= 256, by thread h - 256; tiles with more than 512 halo
-// cells use the direct pull.
+// source value is read (and decoded) 1.3 to 1.5 times per step (the halo over the
+// tile: 324, 340 or 396 cells for 256) instead of up to four times (once per pulling
+// cell).  Two LDS buffers alternate between directions, so one barrier per direction
+// suffices, and the halo values of the next STAGE_AHEAD directions are in flight
+// during each round.  Halo cell h (row-major in the halo tile) is handled by thread h
+// and, for h >= 256, by thread h - 256; tiles with more than 512 halo cells use the
+// direct pull.
 constexpr int STAGED_MAX_HALO = 512;
 
 // source coordinate of a halo position (one step outside the grid at most matters;
