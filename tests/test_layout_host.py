@@ -1,6 +1,9 @@
 """Host-side conversion between (72, ny, nx) populations and the library's buffer
-layouts (no GPU): FP32/FP64 cell records per direction block, and the FP16-deviation
-buffer's rearranged views (SNORM16 deviations, side values, half scales).  Layout as documented in include/rlbm.h."""
+layouts (no GPU): FP32/FP64 cell records per direction block, and the 16-bit
+deviation buffer's views (SNORM16 codes, side values, half scales), as documented in
+include/rlbm.h; and bench.py's naming of the kernel it measures."""
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -54,3 +57,30 @@ def test_dev16_views_layout():
     for j, x, y in [(0, 0, 0), (5, 4, 2), (3, 2, 1)]:
         c = y * nx + x
         assert sc[j, y, x] == scale[6 * c + j]
+
+
+def test_bench_names_the_step_kernel_and_ties_traffic_to_source_and_tile():
+    """bench.py names the kernel its roofline describes (staged pull for FP32 and
+    16-bit populations on tiles whose halo fits 512 cells, direct otherwise) and
+    reports recorded HBM traffic only for the kernel source and tile it was taken on."""
+    import json
+    import bench
+    fd = dict(stats="FD", bc=("open",) * 4)
+    assert bench.step_kernel(fd, "fp32", 5, (64, 4), False) == "k_step_staged<1, float>"
+    assert bench.step_kernel(fd, "dev16", 5, (16, 16), False) == "k_step_staged<1, Dev16>"
+    assert bench.step_kernel(fd, "dev16", 5, (128, 2), False) == "k_step<1, Dev16, float, 5, false>"
+    assert bench.step_kernel(fd, "fp64", 5, (32, 8), False) == "k_step<1, double, double, 5, false>"
+    assert bench.step_kernel(dict(stats="MJ"), "fp32", 3, (32, 8), False) == "k_step<0, float, float, 3, false>"
+    forced = dict(stats="MJ", force=(1e-8, 0.0), bc=("periodic", "periodic", "wall_neq", "wall_neq"))
+    assert bench.step_kernel(forced, "fp32", 5, (64, 4), False) == "k_step<0, float, float, 5, true>"
+    assert bench.step_kernel(dict(stats="MJ"), "fp32", 5, (32, 8), True).startswith("k_step_tiles<0, float, float>")
+    from conftest import ROOT
+    with open(os.path.join(ROOT, "profiles", "hbm_traffic.json")) as fh:
+        rec = json.load(fh)
+    for key, r in rec.items():
+        workload, precision = key.split("/")
+        tile = tuple(int(v) for v in r["tile"].split("x"))
+        other = (256, 1) if tile != (256, 1) else (128, 2)
+        if r["source_sha256"] == bench.kernel_source_hash():
+            assert bench.recorded_traffic(workload, precision, tile) == r["traffic_bytes_per_launch"]
+        assert bench.recorded_traffic(workload, precision, other) is None
