@@ -14,7 +14,8 @@
 * The Fourier-flow set-up of Sec. 3.3 (2048 x 2, 2000 steps, five temperature
   differences, five relaxation times, FP64): the slope a of kappa g_2/g_3 = a tau.
 
-Each run prints its numbers; the design doc records them.
+Each run prints its numbers.  The long reference runs are tests of their own (kept in
+a module cache for the tests after them), so no single test runs for minutes.
 """
 import math
 
@@ -81,43 +82,71 @@ def _errors(got, ref):
     return out
 
 
-def _reduced_precision_errors(rl, make, make_train, steps, label):
+# FP64 reference fields and the trained network of each workload, filled by the
+# reference tests and read by the error tests after them
+_REF = {}
+
+
+def _reference(rl, key, make, make_train, steps, label):
     params, fields = make()
     net = _train_net(rl, make_train)
     ref, st = _run_fields(rl, dict(params, precision="fp64"), fields, steps, f"{label} FP64")
     assert st == 0
-    res = {}
-    for prec, guess in (("fp32", "fixed"), ("dev16", "mlp")):
-        p = dict(params, precision=prec)
-        if guess == "mlp":
-            p.update(guess="mlp", mlp=net.w)
-        got, st = _run_fields(rl, p, fields, steps, f"{label} {prec}")
-        assert st == 0
-        res[prec] = _errors(got, ref)
-        del got
-        print(f"  {label} {prec} ({guess} guess) vs FP64 after {steps} steps: "
-              + ", ".join(f"{k} {v:.2e}" for k, v in res[prec].items()), flush=True)
-    del ref
+    _REF[key] = (ref, net)
+
+
+def _reduced_precision_error(rl, key, make, make_train, prec, steps, label):
+    if key not in _REF:          # run alone (-k): take the reference here
+        _reference(rl, key, make, make_train, steps, label)
+    ref, net = _REF[key]
+    params, fields = make()
+    guess = "fixed" if prec == "fp32" else "mlp"
+    p = dict(params, precision=prec)
+    if guess == "mlp":
+        p.update(guess="mlp", mlp=net.w)
+    got, st = _run_fields(rl, p, fields, steps, f"{label} {prec}")
+    assert st == 0
+    e = _errors(got, ref)
+    del got
+    print(f"  {label} {prec} ({guess} guess) vs FP64 after {steps} steps: "
+          + ", ".join(f"{k} {v:.2e}" for k, v in e.items()), flush=True)
+    assert e["eps_theta"] <= 1e-3 and e["eps_q"] <= 1e-3, (prec, e)
+    for k in ("max_n", "max_eps", "max_theta", "max_z", "max_u"):
+        assert e[k] <= 1e-2, (prec, k, e[k])
+    return e
+
+
+FD_2048 = lambda: workloads.hotspot_fd(L=2048, device="cuda")
+FD_TRAIN = lambda: workloads.hotspot_fd(L=512, seed=11, sigma=16.0, device="cuda")
+BE_8192 = lambda: workloads.hotspot_be(L=8192, device="cuda")
+BE_TRAIN = lambda: workloads.hotspot_be(L=512, seed=11, device="cuda")
+
+
+@pytest.mark.slow
+def test_fd_hotspot_2048_20k_steps_fp64_reference(rl):
+    _reference(rl, "fd", FD_2048, FD_TRAIN, 20000, "FD hot spot 2048^2")
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("prec", ["fp32", "dev16"])
+def test_fd_hotspot_2048_20k_steps_error(rl, prec):
+    _reduced_precision_error(rl, "fd", FD_2048, FD_TRAIN, prec, 20000, "FD hot spot 2048^2")
+
+
+@pytest.mark.slow
+def test_be_hotspot_8192_5k_steps_fp64_reference(rl):
+    _REF.pop("fd", None)
     torch.cuda.empty_cache()
-    for prec, e in res.items():
-        assert e["eps_theta"] <= 1e-3 and e["eps_q"] <= 1e-3, (prec, e)
-        for k in ("max_n", "max_eps", "max_theta", "max_z", "max_u"):
-            assert e[k] <= 1e-2, (prec, k, e[k])
-    return res
+    _reference(rl, "be", BE_8192, BE_TRAIN, 5000, "BE hot spot 8192^2")
 
 
 @pytest.mark.slow
-def test_fd_hotspot_2048_20k_steps_error(rl):
-    _reduced_precision_errors(
-        rl, lambda: workloads.hotspot_fd(L=2048, device="cuda"),
-        lambda: workloads.hotspot_fd(L=512, seed=11, sigma=16.0, device="cuda"), 20000, "FD hot spot 2048^2")
-
-
-@pytest.mark.slow
-def test_be_hotspot_8192_5k_steps_error(rl):
-    _reduced_precision_errors(
-        rl, lambda: workloads.hotspot_be(L=8192, device="cuda"),
-        lambda: workloads.hotspot_be(L=512, seed=11, device="cuda"), 5000, "BE hot spot 8192^2")
+@pytest.mark.parametrize("prec", ["fp32", "dev16"])
+def test_be_hotspot_8192_5k_steps_error(rl, prec):
+    _reduced_precision_error(rl, "be", BE_8192, BE_TRAIN, prec, 5000, "BE hot spot 8192^2")
+    if prec == "dev16":
+        _REF.pop("be", None)
+        torch.cuda.empty_cache()
 
 
 def _decay_fit(ts, sig, L, t0, t1):
