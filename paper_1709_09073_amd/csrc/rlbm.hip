@@ -88,6 +88,7 @@ struct KArgs {
     int nx, ny;
     long long plane;             // nx*ny
     int tx, ty, ntx, ntiles, per_xcd;
+    int nty, sw;                 // tile rows; tile columns per strip (tile order below)
     int bc_xlo, bc_xhi, bc_ylo, bc_yhi;
     int tau_mode;
     double tau, tau_a, tau_b;
@@ -109,16 +110,32 @@ struct KArgs {
 };
 
 // ---------------------------------------------------------------- tile mapping
-// Tiles are numbered row-major; the hardware hands consecutive workgroups to the
-// 8 XCDs in turn, so workgroup b runs tile (b % 8) * per_xcd + b / 8: each XCD
-// sweeps its own contiguous band of tile rows and the one-cell halos between
-// neighbouring tiles stay inside that XCD's L2.
+// Tiles are numbered strip by strip: a strip is sw tile columns wide (about
+// RLBM_STRIP_CELLS cells for staged-pull launches; the whole grid width, i.e. plain
+// row order, for direct-pull ones), swept row by row from top to bottom.  The hardware
+// hands consecutive workgroups to the 8 XCDs in turn, so workgroup b runs tile
+// (b % 8) * per_xcd + b / 8: each XCD sweeps its own contiguous run of strip rows.  The
+// tile above a tile ran sw tiles earlier on the same XCD, so the halo rows they share
+// are still in that XCD's L2 even on grids too wide for a whole tile row to stay there.
+#ifndef RLBM_STRIP_CELLS
+#define RLBM_STRIP_CELLS 1024
+#endif
+
+__device__ __forceinline__ void tile_xy(const KArgs &a, int t, int &txi, int &tyi) {
+    const int per_strip = a.sw * a.nty;
+    const int s = t / per_strip;
+    const int r = t - s * per_strip;
+    const int w = min(a.sw, a.ntx - s * a.sw);
+    tyi = r / w;
+    txi = s * a.sw + (r - tyi * w);
+}
+
 __device__ __forceinline__ bool cell_of(const KArgs &a, int &x, int &y) {
     const int b = blockIdx.x;
     const int t = (b & 7) * a.per_xcd + (b >> 3);
     if (t >= a.ntiles) return false;
-    const int tyi = t / a.ntx;
-    const int txi = t - tyi * a.ntx;
+    int txi, tyi;
+    tile_xy(a, t, txi, tyi);
     const int lx = threadIdx.x % a.tx;
     const int ly = threadIdx.x / a.tx;
     x = txi * a.tx + lx;
@@ -1417,8 +1434,9 @@ __global__ RLBM_STEP_BOUNDS(ST, float, false) void k_step_staged(KArgs a) {
     const int b = blockIdx.x;
     const int t = (b & 7) * a.per_xcd + (b >> 3);
     if (t >= a.ntiles) return;                 // the whole workgroup leaves together
-    const int tyi = t / a.ntx;
-    staged_tile<ST, S>(a, t - tyi * a.ntx, tyi, stage_lds);
+    int txi, tyi;
+    tile_xy(a, t, txi, tyi);
+    staged_tile<ST, S>(a, txi, tyi, stage_lds);
 }
 
 // Many grids in one launch.  The tiles of all grids are numbered consecutively
@@ -1446,8 +1464,8 @@ __global__ RLBM_BATCH_BOUNDS(ST, R) void k_step_batch(Batch b, const KArgs *__re
         const int g = __builtin_amdgcn_readfirstlane(tile_grid[t]);
         const KArgs a = descs[g];
         const int lt = t - __builtin_amdgcn_readfirstlane(tile_base[g]);
-        const int tyi = lt / a.ntx;
-        const int txi = lt - tyi * a.ntx;
+        int txi, tyi;
+        tile_xy(a, lt, txi, tyi);
         if constexpr (!std::is_same<S, double>::value) {
             if (b.staged) {
                 extern __shared__ float stage_lds[];
@@ -1476,8 +1494,8 @@ __global__ RLBM_STEP_BOUNDS(ST, R, false) void k_step_tiles(Batch b, const KArgs
     const int g = __builtin_amdgcn_readfirstlane(tile_grid[t]);
     const KArgs a = descs[g];
     const int lt = t - __builtin_amdgcn_readfirstlane(tile_base[g]);
-    const int tyi = lt / a.ntx;
-    const int txi = lt - tyi * a.ntx;
+    int txi, tyi;
+    tile_xy(a, lt, txi, tyi);
     if constexpr (!std::is_same<S, double>::value) {
         if (b.staged) {
             extern __shared__ float stage_lds[];
@@ -1683,11 +1701,12 @@ KFn pick_staged(int st, int prec) {
 }
 
 // dynamic LDS of the staged pull for tiles of tx x ty, 0 where the direct pull runs:
-// FP64 populations, and tiles whose halo exceeds STAGED_MAX_HALO cells
-size_t staged_lds_bytes(int prec, int tx, int ty) {
+// FP64 populations, lower orders, forcing, and tiles whose halo exceeds
+// STAGED_MAX_HALO cells
+size_t staged_lds_bytes(const rlbm_params &p, int tx, int ty) {
     const int nh = (tx + 2) * (ty + 2);
-    const bool staged = prec == RLBM_DEV16 || (prec == RLBM_FP32 && RLBM_FP32_STAGED);
-    if (!staged || nh > STAGED_MAX_HALO) return 0;
+    const bool staged = p.precision == RLBM_DEV16 || (p.precision == RLBM_FP32 && RLBM_FP32_STAGED);
+    if (!staged || nh > STAGED_MAX_HALO || p.order != 5 || is_forced(p)) return 0;
     return sizeof(float) * 12 * (size_t)nh;
 }
 
@@ -1826,12 +1845,18 @@ KArgs make_base(const rlbm_params &p, rlbm_ctx *c) {
     return a;
 }
 
-void set_tiles(KArgs &a, int tx, int ty) {
+// strips: order the tiles in strips (staged-pull launches) or by rows (direct pull,
+// whose 128x2 and 256x1 tiles ran 4% slower in strips on an 8192-wide grid, while 64x4
+// staged tiles ran 2% faster)
+void set_tiles(KArgs &a, int tx, int ty, bool strips = false) {
     a.tx = tx;
     a.ty = ty;
     a.ntx = (a.nx + tx - 1) / tx;
-    a.ntiles = a.ntx * ((a.ny + ty - 1) / ty);
+    a.nty = (a.ny + ty - 1) / ty;
+    a.ntiles = a.ntx * a.nty;
     a.per_xcd = (a.ntiles + 7) / 8;
+    // strip width in tiles (at least one tile; a strip as wide as the grid is row order)
+    a.sw = (strips && RLBM_STRIP_CELLS > 0) ? std::min(a.ntx, std::max(1, RLBM_STRIP_CELLS / tx)) : a.ntx;
 }
 
 void drop_graphs(rlbm_ctx *c) {
@@ -1861,7 +1886,7 @@ int configure(rlbm_ctx *c, int tx, int ty) {
     drop_graphs(c);
     c->tx = tx;
     c->ty = ty;
-    for (auto &a : c->base) set_tiles(a, tx, ty);
+    for (auto &a : c->base) set_tiles(a, tx, ty, staged_lds_bytes(c->p[0], tx, ty) > 0);
     if (!c->batch) return RLBM_OK;
     const int ng = (int)c->base.size();
     std::vector<int> tbase(ng + 1, 0);
@@ -1904,7 +1929,7 @@ int launch_step(rlbm_ctx *c, hipStream_t s) {
         b.groups_per_xcd = c->batch_groups_per_xcd;
         const KArgs *descs = c->d_descs + (size_t)c->cur * c->base.size();
         const bool persistent = b.groups_per_xcd < b.per_xcd;
-        const size_t lds = staged_lds_bytes(p0.precision, c->tx, c->ty);
+        const size_t lds = staged_lds_bytes(p0, c->tx, c->ty);
         b.staged = lds > 0;
         hipLaunchKernelGGL(pick_batch(p0.stats, p0.precision, persistent), dim3(8 * b.groups_per_xcd), dim3(256), lds, s,
                            b, descs, (const int *)c->d_tile_grid, (const int *)c->d_tile_base);
@@ -1912,9 +1937,7 @@ int launch_step(rlbm_ctx *c, hipStream_t s) {
         KArgs a = c->base[0];
         a.fin = c->cur ? p0.f_b : p0.f_a;
         a.fout = c->cur ? p0.f_a : p0.f_b;
-        // the staged pull covers order 5 without forcing (16-bit deviations are
-        // only that, checked at create)
-        const size_t lds = (is_forced(p0) || p0.order != 5) ? 0 : staged_lds_bytes(p0.precision, c->tx, c->ty);
+        const size_t lds = staged_lds_bytes(p0, c->tx, c->ty);
         if (lds > 0) {
             hipLaunchKernelGGL(pick_staged(p0.stats, p0.precision), dim3(8 * a.per_xcd), dim3(256), lds, s, a);
         } else {
