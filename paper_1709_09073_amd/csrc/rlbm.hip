@@ -871,10 +871,11 @@ __device__ __forceinline__ void dev_decode(const DecodeRef &d, const u32x3 &q, f
 }
 
 // Bilinear interpolation of direction N's six shells from the decoded sources at
-// (xb, yb), (x, yb), (xb, y), (x, y): the same weights and order as the FP32 pull.
+// (xb, yb), (x, yb), (xb, y), (x, y): the same weights and order as the direct FP32
+// pull (used by the 16-bit direct pull and by the staged pull of both formats).
 template <int N>
-__device__ __forceinline__ void dev_interp(const float (&bb)[6], const float (&bx)[6], const float (&cb)[6],
-                                           const float (&cx)[6], float (&f)[72]) {
+__device__ __forceinline__ void bilinear_direction(const float (&bb)[6], const float (&bx)[6],
+                                                   const float (&cb)[6], const float (&cx)[6], float (&f)[72]) {
     const float wA = (float)(S3H * 0.5), wB = (float)((1.0 - S3H) * 0.5);
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
@@ -912,7 +913,7 @@ __device__ __forceinline__ void dev_pull_direction(const char *base, rsrc_t rs, 
         dev_tap<ST, N>(base, rs, plane, rb + x, bx);
         dev_tap<ST, N>(base, rs, plane, oc + xb, cb);
         dev_tap<ST, N>(base, rs, plane, oc + x, cx);
-        dev_interp<N>(bb, bx, cb, cx, f);
+        bilinear_direction<N>(bb, bx, cb, cx, f);
     }
 }
 
@@ -1057,7 +1058,7 @@ __device__ __forceinline__ void lds_direction(const float *buf, int hw, int hx, 
         lds_read_tap(buf, yb * hw + hx, bx);
         lds_read_tap(buf, hy * hw + xb, cb);
         lds_read_tap(buf, hy * hw + hx, cx);
-        dev_interp<N>(bb, bx, cb, cx, f);
+        bilinear_direction<N>(bb, bx, cb, cx, f);
     }
 }
 
