@@ -944,10 +944,10 @@ __device__ __forceinline__ void pull_dev(const void *fin, long long plane, int n
 // source value is read (and decoded) 1.3 to 1.5 times per step (the halo over the
 // tile: 324, 340 or 396 cells for 256) instead of up to four times (once per pulling
 // cell).  Two LDS buffers alternate between directions, so one barrier per direction
-// suffices, and the halo values of the next STAGE_AHEAD directions are in flight
-// during each round.  Halo cell h (row-major in the halo tile) is handled by thread h
-// and, for h >= 256, by thread h - 256; tiles with more than 512 halo cells use the
-// direct pull.
+// suffices, and the halo values of the next two (FP32) or three (16-bit) directions
+// are in flight during each round.  Halo cell h (row-major in the halo tile) is
+// handled by thread h and, for h >= 256, by thread h - 256; tiles with more than 512
+// halo cells use the direct pull.
 constexpr int STAGED_MAX_HALO = 512;
 
 // source coordinate of a halo position (one step outside the grid at most matters;
@@ -1063,20 +1063,20 @@ __device__ __forceinline__ void lds_direction(const float *buf, int hw, int hx, 
 }
 
 // Directions whose halo values are in flight while a round works (register cost:
-// STAGE_AHEAD x 2 halo slots x 3 (16-bit deviations) or 6 (FP32) registers).
-#ifndef RLBM_STAGE_AHEAD
-#define RLBM_STAGE_AHEAD 2
-#endif
-constexpr int STAGE_AHEAD = RLBM_STAGE_AHEAD;
+// depth x 2 halo slots x 3 (16-bit deviations) or 6 (FP32) registers).  Measured: FP32
+// best at 2 (3: -0.1%), 16-bit deviations at 3 (+0.5 to +1% over 2).
+template <typename S>
+constexpr int STAGE_AHEAD = std::is_same<S, Dev16>::value ? 3 : 2;
 
 // One direction of the staged pull: q[i] holds direction N + i's halo values (requested
-// in earlier rounds); direction N + STAGE_AHEAD's are requested first.
+// in earlier rounds); direction N + STAGE_AHEAD<S>'s are requested first.
 template <int ST, typename S, int N>
 __device__ __forceinline__ void stage_round(const void *fin, long long plane, const HaloCell<ST, S> (&hc)[2], int tid,
                                             float *lds, int nh, int hw, int hx, int hy, bool use,
-                                            typename Stage<ST, S>::Raw (&q)[STAGE_AHEAD][2], float (&f)[72]) {
+                                            typename Stage<ST, S>::Raw (&q)[STAGE_AHEAD<S>][2], float (&f)[72]) {
+    constexpr int D = STAGE_AHEAD<S>;
     typename Stage<ST, S>::Raw qn[2];
-    if constexpr (N + STAGE_AHEAD < 12) stage_load<ST, S, N + STAGE_AHEAD>(fin, plane, hc, qn);
+    if constexpr (N + D < 12) stage_load<ST, S, N + D>(fin, plane, hc, qn);
     float *buf = lds + (N & 1) * 6 * nh;
     stage_write<ST, S, N>(hc, q[0], tid, buf);
     __syncthreads();
@@ -1084,15 +1084,15 @@ __device__ __forceinline__ void stage_round(const void *fin, long long plane, co
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
 #pragma unroll
-        for (int i = 0; i + 1 < STAGE_AHEAD; ++i) q[i][j] = q[i + 1][j];
-        if constexpr (N + STAGE_AHEAD < 12) q[STAGE_AHEAD - 1][j] = qn[j];
+        for (int i = 0; i + 1 < D; ++i) q[i][j] = q[i + 1][j];
+        if constexpr (N + D < 12) q[D - 1][j] = qn[j];
     }
 }
 
 template <int ST, typename S, int I>
 __device__ __forceinline__ void stage_prime(const void *fin, long long plane, const HaloCell<ST, S> (&hc)[2],
-                                            typename Stage<ST, S>::Raw (&q)[STAGE_AHEAD][2]) {
-    if constexpr (I < STAGE_AHEAD) {
+                                            typename Stage<ST, S>::Raw (&q)[STAGE_AHEAD<S>][2]) {
+    if constexpr (I < STAGE_AHEAD<S>) {
         stage_load<ST, S, I>(fin, plane, hc, q[I]);
         stage_prime<ST, S, I + 1>(fin, plane, hc, q);
     }
@@ -1118,7 +1118,7 @@ __device__ __forceinline__ void staged_pull(const KArgs &a, int x0, int y0, floa
         hc[j].cell = hc[j].valid ? (unsigned)(sy * a.nx + sx) : 0u;
         Stage<ST, S>::side(a.fin, a.plane, hc[j].cell, hc[j].side);
     }
-    typename Stage<ST, S>::Raw q[STAGE_AHEAD][2];
+    typename Stage<ST, S>::Raw q[STAGE_AHEAD<S>][2];
     stage_prime<ST, S, 0>(a.fin, a.plane, hc, q);
     stage_round<ST, S, 0>(a.fin, a.plane, hc, tid, lds, nh, hw, hx, hy, use, q, f);
     stage_round<ST, S, 1>(a.fin, a.plane, hc, tid, lds, nh, hw, hx, hy, use, q, f);
