@@ -127,7 +127,7 @@ def pack_populations(f, precision):
     elif precision == "fp64":
         out = rec.reshape(12, P, 3, 2).permute(0, 2, 1, 3)
     else:
-        raise ValueError("FP16-deviation buffers cannot be packed from populations")
+        raise ValueError("16-bit deviation buffers cannot be packed from populations")
     return out.reshape(-1).contiguous()
 
 
