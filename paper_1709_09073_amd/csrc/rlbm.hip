@@ -1815,8 +1815,9 @@ void auto_tile(const rlbm_params &p, int &tx, int &ty) {
         ty = p.tile_y;
         return;
     }
-    // Measured on MI355X: 32 x 8 is fastest on 2048-wide grids, while on 8192-wide
-    // grids 128 x 2 runs about 30% faster than 32 x 8.  rlbm_autotune measures instead.
+    // Defaults when no tile is given (rlbm_autotune measures instead): 128 x 2 (direct
+    // pull) on grids 4096 or more cells wide, where it ran fastest on an 8192-wide grid;
+    // otherwise rows of 8, 4 or 2 cells (the staged pull where the halo fits).
     if (p.nx >= 4096 && p.ny >= 2) {
         tx = 128;
         ty = 2;
