@@ -426,18 +426,41 @@ __device__ __forceinline__ void g_tail(double mu, double xi, double (&g)[7]) {
     }
 }
 
+// One table centre's coefficients held in registers: columns 0 .. K+4 of its row, the
+// ones orders 1..6 read.  The Newton iterates of one cell and its final evaluation
+// usually fall on the same centre; with REUSE they then take the row from registers
+// instead of reading it again, a dependent load the cell would otherwise wait for
+// each time.  (Fermi-Dirac with FP32 or 16-bit populations only: the other kernels
+// have no registers to spare for the row.)
+template <int K>
+struct GRow {
+    int i;   // centre index held; -1: none
+    double c[K + 5];
+};
+
+template <bool LOOSE>
+using GRowT = GRow<LOOSE ? NT_LOOSE : NT>;
+
+template <bool REUSE, int K>
+__device__ __forceinline__ void g_row_fetch(const double (*tab)[NG], int i, GRow<K> &row) {
+    if (REUSE && i == row.i) return;
+    const double *src = tab[i];
+#pragma unroll
+    for (int j = 0; j < K + 5; ++j) row.c[j] = src[j];
+    row.i = i;
+}
+
 template <int MLO, int MHI, int K>
-__device__ __forceinline__ void g_table(const double (*tab)[NG], int i, double d, double (&g)[7]) {
+__device__ __forceinline__ void g_table(const GRow<K> &row, double d, double (&g)[7]) {
     double t[K];
     t[0] = 1.0;
 #pragma unroll
     for (int k = 1; k < K; ++k) t[k] = t[k - 1] * (d * (1.0 / k));   // d / k off the dependency chain
-    const double *row = tab[i];
 #pragma unroll
     for (int m = MLO; m <= MHI; ++m) {
         double s = 0;
 #pragma unroll
-        for (int k = K - 1; k >= 0; --k) s += row[6 - m + k] * t[k];
+        for (int k = K - 1; k >= 0; --k) s += row.c[6 - m + k] * t[k];
         g[m] = s;
     }
 }
@@ -445,7 +468,7 @@ __device__ __forceinline__ void g_table(const double (*tab)[NG], int i, double d
 // LOOSE (FP32 / 16-bit populations): shortened sums, tail below 1e-11 relative
 // (bounded when the tables are generated).
 template <int ST, int MLO, int MHI, bool LOOSE = false>
-__device__ __forceinline__ void gvals(double mu, double (&g)[7], unsigned &flags) {
+__device__ __forceinline__ void gvals(double mu, double (&g)[7], unsigned &flags, GRowT<LOOSE> &row) {
     constexpr int K = LOOSE ? NT_LOOSE : NT;
     constexpr int NZ = LOOSE ? BE_NZ_LOOSE : BE_NZ;
     // table indices below are formed from mu: keep it finite and inside the tables' reach
@@ -469,7 +492,8 @@ __device__ __forceinline__ void gvals(double mu, double (&g)[7], unsigned &flags
             i = FD_NC - 1;
             if (mu > FD_MU_MIN + (FD_NC - 0.5) * FD_DMU) flags |= RLBM_FLAG_RANGE;
         }
-        g_table<MLO, MHI, K>(FD_TAB, i, mu - (FD_MU_MIN + i * FD_DMU), g);
+        g_row_fetch<LOOSE>(FD_TAB, i, row);
+        g_table<MLO, MHI, K>(row, mu - (FD_MU_MIN + i * FD_DMU), g);
     } else {
         if (mu < BE_MU_MIN - 0.5 * BE_DMU) {
             g_tail<MLO, MHI>(mu, -1.0, g);
@@ -478,7 +502,8 @@ __device__ __forceinline__ void gvals(double mu, double (&g)[7], unsigned &flags
         if (mu < BE_MU_SPLIT - 0.5 * BE_DMU) {
             int i = (int)rint((mu - BE_MU_MIN) * (1.0 / BE_DMU));
             if (i > BE_NC - 1) i = BE_NC - 1;
-            g_table<MLO, MHI, K>(BE_TAB, i, mu - (BE_MU_MIN + i * BE_DMU), g);
+            g_row_fetch<false>(BE_TAB, i, row);
+            g_table<MLO, MHI, K>(row, mu - (BE_MU_MIN + i * BE_DMU), g);
             return;
         }
         // Li_m(e^mu) = mu^{m-1}/(m-1)! (H_{m-1} - ln(-mu)) + sum_{k != m-1} zeta(m-k) mu^k / k!
@@ -497,6 +522,13 @@ __device__ __forceinline__ void gvals(double mu, double (&g)[7], unsigned &flags
     }
 }
 
+template <int ST, int MLO, int MHI, bool LOOSE = false>
+__device__ __forceinline__ void gvals(double mu, double (&g)[7], unsigned &flags) {
+    GRowT<LOOSE> row;
+    row.i = -1;
+    gvals<ST, MLO, MHI, LOOSE>(mu, g, flags, row);
+}
+
 // Newton on mu = ln z leaves an error C dmu^2 after a step dmu, with C = f''/(2 f')
 // at most 0.5 for FD and about 0.5/|mu| for BE near mu = 0, so a step below this
 // tolerance is applied and ends the solve (no confirming evaluation).  FP64
@@ -509,8 +541,9 @@ __device__ __forceinline__ double newton_tol(double mu) {
 }
 
 // Solve h(mu) = g_2^3/g_3^2 = r for mu = ln z (FD, BE), safeguarded Newton.
+// row: the table row of the last evaluation, for the caller's final evaluation at the root.
 template <int ST, bool LOOSE>
-__device__ __forceinline__ double invert_h(double r, double mu, unsigned &flags, int &iters) {
+__device__ __forceinline__ double invert_h(double r, double mu, unsigned &flags, int &iters, GRowT<LOOSE> &row) {
     double lo = -40.0, hi = (ST == RLBM_BE) ? LOG_ZC_BE : FD_MU_MIN + (FD_NC - 0.5) * FD_DMU;
     if (ST == RLBM_BE && r >= H_ZC_BE) {
         flags |= RLBM_FLAG_CONDENSED;
@@ -522,7 +555,7 @@ __device__ __forceinline__ double invert_h(double r, double mu, unsigned &flags,
     for (int it = 0; it < 80; ++it) {
         ++iters;
         double g[7];
-        gvals<ST, 1, 3, LOOSE>(mu, g, flags);
+        gvals<ST, 1, 3, LOOSE>(mu, g, flags, row);
         double h, dmu;
         if constexpr (LOOSE) {
             // one FP64 reciprocal (1-2 ulp); the step itself only needs single precision: its
@@ -627,8 +660,10 @@ __device__ __forceinline__ void state_from_moments(const Mom &m, Macro &M, unsig
         // starting point of the Newton solve: the trained network, or the fixed guess
         double mu0 = (ST == RLBM_BE) ? -0.6931471805599453 : 0.0;
         if (a.guess == RLBM_GUESS_MLP) mu0 = (double)rlbm_mlp::eval(a.mlp, logf((float)r));
-        const double mu = invert_h<ST, LOOSE>(r, mu0, flags, iters);
-        gvals<ST, 1, 6, LOOSE>(mu, M.g, flags);
+        GRowT<LOOSE> row;
+        row.i = -1;
+        const double mu = invert_h<ST, LOOSE>(r, mu0, flags, iters, row);
+        gvals<ST, 1, 6, LOOSE>(mu, M.g, flags, row);
         M.z = exp(mu);
         if constexpr (LOOSE) M.theta = qdiv<LOOSE>(0.5 * M.g[2] * M.eps, M.g[3] * M.n);
         else M.theta = 0.5 * (M.g[2] / M.g[3]) * (M.eps / M.n);
