@@ -430,8 +430,9 @@ __device__ __forceinline__ void g_tail(double mu, double xi, double (&g)[7]) {
 // ones orders 1..6 read.  The Newton iterates of one cell and its final evaluation
 // usually fall on the same centre; with REUSE they then take the row from registers
 // instead of reading it again, a dependent load the cell would otherwise wait for
-// each time.  (Fermi-Dirac with FP32 or 16-bit populations only: the other kernels
-// have no registers to spare for the row.)
+// each time.  (Fermi-Dirac with FP32 or 16-bit populations only: the Bose-Einstein
+// kernels have no registers to spare for the row, and the FP64 step, one wave per
+// SIMD, ran no faster with it.)
 template <int K>
 struct GRow {
     int i;   // centre index held; -1: none
