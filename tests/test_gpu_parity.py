@@ -242,6 +242,39 @@ def test_fp64_fugacity_across_every_branch(rl, stats):
     assert r <= 1.0
 
 
+@pytest.mark.parametrize("stats", ["FD", "BE"])
+def test_fp32_fugacity_across_every_branch(rl, stats):
+    """The same z sweep with FP32 populations and the fixed Newton start (mu = 0 FD,
+    ln 1/2 BE): the Newton iterates walk across many table centres, so the FP32
+    inversion's row kept in registers between evaluations is replaced whenever the
+    centre changes (a stale row would be off by orders of magnitude).  Bars from the
+    2^-24 storage rounding of each step, cell by cell: n, eps 2e-6 x steps, z and theta
+    with the conditioning kappa as above, u 2e-5 of max(|u|, 0.01), populations 1e-5 of
+    w_k max_i |f_i/w_k| of their own cell."""
+    nx, ny, nsteps = 64, 5, 3
+    fields = workloads.fugacity_ramp(nx, ny, seed=7, stats=stats)
+    params = dict(nx=nx, ny=ny, bc=("open", "open", "periodic", "periodic"), tau=0.9)
+    pops, flds, fo, flo = _run(rl, stats, "fp32", params, fields, nsteps)
+    g = G.g_all(stats, flo["z"])
+    kappa = 1.0 / np.abs(3 * g[0] / g[1] - 2 * g[1] / g[2])
+    base = 2e-6 * nsteps
+    bars = dict(n=base, eps=base, z=base * (1 + 5 * kappa),
+                theta=base * (2 + 5 * kappa * np.abs(g[0] / g[1] - g[1] / g[2])))
+    for k, bar in bars.items():
+        r = (_cellwise(flds[k], flo[k]) / bar).max()
+        print(f"  {stats} fp32 z sweep: {k} worst cell error / bar {r:.3f}")
+        assert r <= 1.0, (k, r)
+    du = np.maximum(np.abs(flds["ux"] - flo["ux"]), np.abs(flds["uy"] - flo["uy"])).max()
+    ubar = 2e-5 * max(np.abs(flo["ux"]).max(), np.abs(flo["uy"]).max(), 0.01)
+    print(f"  {stats} fp32 z sweep: max |u - u_oracle| {du:.2e} (bar {ubar:.1e})")
+    assert du <= ubar
+    w = Q.vectors(stats)["w"][:, None, None]
+    M = np.abs(fo / w).max(axis=0)
+    r = (np.abs(pops - fo) / (w * M) / 1e-5).max()
+    print(f"  {stats} fp32 z sweep: populations worst error / (1e-5 w_k M_cell) {r:.3f}")
+    assert r <= 1.0
+
+
 def test_fd_table_range_flag(rl):
     """FD fugacity beyond the tables (ln z > 12.125) is reported, not silently used."""
     nx, ny = 16, 4
