@@ -435,6 +435,7 @@ __device__ __forceinline__ void g_tail(double mu, double xi, double (&g)[7]) {
 // SIMD, ran no faster with it.)
 template <int K>
 struct GRow {
+    static_assert(K + 5 <= NG, "orders 1..6 with K Taylor terms read columns 0 .. K+4 of a row");
     int i;   // centre index held; -1: none
     double c[K + 5];
 };
