@@ -194,18 +194,20 @@ def test_results_do_not_depend_on_the_tile(rl, precision, nx):
             assert same_bits(st, ref), t
 
 
+@pytest.mark.parametrize("stats", ["MJ", "FD"])
 @pytest.mark.parametrize("precision", ["fp32", "dev16"])
-def test_batch_launch_modes_agree(rl, precision):
+def test_batch_launch_modes_agree(rl, precision, stats):
     """One workgroup per tile and the persistent sweep, for every tile shape, give the
-    same bits: the two modes are separate kernels (their own register budgets and
-    instruction schedules) over the same arithmetic, and a*b + c is fused only within
-    one source expression, so no kernel rounds differently."""
-    grids = _grids(stats="MJ", precision=precision)
+    same bits, and so does a single-grid context: the modes are separate kernels (their
+    own register budgets and instruction schedules) over the same arithmetic, and a*b + c
+    is fused only within one source expression, so no kernel rounds differently.  (FD:
+    the inversion keeps a table row in registers between evaluations in every kernel.)"""
+    grids = _grids(stats=stats, precision=precision)
     b = rl.Batch([g[0] for g in grids], [{k: v.cuda() for k, v in g[1].items()} for g in grids])
     b.step(5)
     saved = [b.state(i).clone() for i in range(len(grids))]
     ref = {}
-    print(f"[batch] {precision}: {len(TILES)} tile shapes x 2 launch modes, 4 steps", flush=True)
+    print(f"[batch] {stats} {precision}: {len(TILES)} tile shapes x 2 launch modes, 4 steps", flush=True)
     for persistent in (0, 96):
         for t in TILES:
             for i in range(len(grids)):
@@ -221,6 +223,11 @@ def test_batch_launch_modes_agree(rl, precision):
     for i in range(len(grids)):
         assert same_bits(ref[0][i], ref[96][i]), i
     b.close()
+    for i, (p, f) in enumerate(grids):
+        s = rl.Sim(p, {k: v.cuda() for k, v in f.items()})
+        s.step(9)
+        assert same_bits(s.state(), ref[96][i]), ("single grid", i)
+        s.close()
 
 
 @pytest.mark.parametrize("precision", ["fp32", "dev16"])
